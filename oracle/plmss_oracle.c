@@ -1,0 +1,372 @@
+/*
+ * plmss_oracle.c -- serial CPU oracle for the piecewise-linear Morse-Smale
+ * segmentation (Maack et al., "Parallel Computation of Piecewise Linear
+ * Morse-Smale Segmentations", arXiv 2303.15491).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
+ * definition that the GPU library is checked against.  It shares no code,
+ * header, table or helper with the GPU library, and only the test suite, the
+ * smoke check and the benchmark's CPU-baseline leg may load it.
+ *
+ * Domain (paper, Sec. "Input Data" and the caption of Table 2): a regular
+ * nx x ny x nz vertex grid, vertex id v = x + nx*(y + ny*z), cut into six
+ * tetrahedra per cube.  The cut used here is the Freudenthal/Kuhn one whose
+ * cube diagonal is (1,1,1); its 2-D restriction is the (+1,+1) diagonal drawn
+ * in the paper's Fig. 1 (fig:wallmodes).  A vertex is joined by an edge to the
+ * vertices at the offsets {(a,b,c) in {0,1}^3, not all zero} and their
+ * negatives: 14 in 3-D, 6 in 2-D (nz = 1), 2 in 1-D.  No wrap-around.
+ *
+ * Every function is serial, allocates with malloc, and reports failure through
+ * its return code (see ORC_* below).  All arrays are host memory owned by the
+ * caller.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_E_ARG (-1)
+#define ORC_E_DIMS (-2)
+#define ORC_E_TOO_LARGE (-3)
+#define ORC_E_NAN (-4)
+#define ORC_E_NOMEM (-7)
+
+/* The seven edge directions of the Freudenthal cube; the full neighbourhood
+ * is these and their negatives. */
+static const int EDGE_DIR[7][3] = {
+    {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}, {1, 1, 1}};
+
+typedef struct {
+    int64_t nx, ny, nz, n;
+} grid_t;
+
+static int make_grid(int64_t nx, int64_t ny, int64_t nz, grid_t* g) {
+    if (nx < 1 || ny < 1 || nz < 1) return ORC_E_DIMS;
+    if (nx > INT32_MAX || ny > INT32_MAX || nz > INT32_MAX) return ORC_E_TOO_LARGE;
+    g->nx = nx;
+    g->ny = ny;
+    g->nz = nz;
+    g->n = nx * ny;
+    if (g->n > INT32_MAX || g->n * nz > INT32_MAX) return ORC_E_TOO_LARGE;
+    g->n *= nz;
+    return ORC_OK;
+}
+
+/* Writes the ids of the in-grid neighbours of v into nb[]; returns how many. */
+static int neighbours(const grid_t* g, int64_t v, int64_t nb[14]) {
+    int64_t x = v % g->nx, y = (v / g->nx) % g->ny, z = v / (g->nx * g->ny);
+    int k = 0;
+    for (int d = 0; d < 7; ++d) {
+        for (int s = -1; s <= 1; s += 2) {
+            int64_t xx = x + s * EDGE_DIR[d][0];
+            int64_t yy = y + s * EDGE_DIR[d][1];
+            int64_t zz = z + s * EDGE_DIR[d][2];
+            if (xx < 0 || yy < 0 || zz < 0 || xx >= g->nx || yy >= g->ny || zz >= g->nz) continue;
+            nb[k++] = xx + g->nx * (yy + g->ny * zz);
+        }
+    }
+    return k;
+}
+
+/* Field value widened to double: exact for float32, identity for float64. */
+static double value(const void* f, int dtype, int64_t v) {
+    return dtype == 0 ? (double)((const float*)f)[v] : ((const double*)f)[v];
+}
+
+static int has_nan(const void* f, int dtype, int64_t n) {
+    for (int64_t v = 0; v < n; ++v) {
+        double a = value(f, dtype, v);
+        if (a != a) return 1;
+    }
+    return 0;
+}
+
+/* Simulation of Simplicity comparison (paper, Sec. "Preprocessing"): u comes
+ * after w in the global vertex order iff f(u) > f(w), or the values are equal
+ * and u has the larger index.  IEEE comparison, so -0 and +0 are equal. */
+static int sos_after(const void* f, int dtype, int64_t u, int64_t w) {
+    double a = value(f, dtype, u), b = value(f, dtype, w);
+    if (a > b) return 1;
+    if (a < b) return 0;
+    return u > w;
+}
+
+typedef struct {
+    double val;
+    int64_t idx;
+} keyed_t;
+
+static int cmp_keyed(const void* pa, const void* pb) {
+    const keyed_t* a = (const keyed_t*)pa;
+    const keyed_t* b = (const keyed_t*)pb;
+    if (a->val < b->val) return -1;
+    if (a->val > b->val) return 1;
+    return (a->idx > b->idx) - (a->idx < b->idx);
+}
+
+static int cmp_u64(const void* pa, const void* pb) {
+    uint64_t a = *(const uint64_t*)pa, b = *(const uint64_t*)pb;
+    return (a > b) - (a < b);
+}
+
+/*
+ * Order field (paper, Sec. "Preprocessing"): sort the vertices by value,
+ * breaking ties by vertex index, and give each vertex its position in that
+ * sorted array.  perm (nullable) receives the sorted array itself.
+ */
+int plmss_oracle_order(const void* f, int dtype, int64_t nx, int64_t ny, int64_t nz,
+                       int32_t* order, int32_t* perm) {
+    grid_t g;
+    int rc = make_grid(nx, ny, nz, &g);
+    if (rc) return rc;
+    if (!f || !order || (dtype != 0 && dtype != 1)) return ORC_E_ARG;
+    if (has_nan(f, dtype, g.n)) return ORC_E_NAN;
+    keyed_t* a = (keyed_t*)malloc(sizeof(keyed_t) * (size_t)g.n);
+    if (!a) return ORC_E_NOMEM;
+    for (int64_t v = 0; v < g.n; ++v) {
+        a[v].val = value(f, dtype, v);
+        a[v].idx = v;
+    }
+    qsort(a, (size_t)g.n, sizeof(keyed_t), cmp_keyed);
+    for (int64_t i = 0; i < g.n; ++i) {
+        order[a[i].idx] = (int32_t)i;
+        if (perm) perm[i] = (int32_t)a[i].idx;
+    }
+    free(a);
+    return ORC_OK;
+}
+
+/*
+ * Steepest neighbours (paper, Sec. "Ascending and Descending Segmentation"):
+ * up[v] is the neighbour with the largest order value, dn[v] the one with the
+ * smallest.  A vertex with no larger (smaller) neighbour is a maximum
+ * (minimum) and points to itself.
+ */
+int plmss_oracle_steepest(const int32_t* order, int64_t nx, int64_t ny, int64_t nz,
+                          int32_t* up, int32_t* dn) {
+    grid_t g;
+    int rc = make_grid(nx, ny, nz, &g);
+    if (rc) return rc;
+    if (!order || !up || !dn) return ORC_E_ARG;
+    int64_t nb[14];
+    for (int64_t v = 0; v < g.n; ++v) {
+        int k = neighbours(&g, v, nb);
+        int64_t hi = v, lo = v;
+        for (int i = 0; i < k; ++i) {
+            if (order[nb[i]] > order[hi]) hi = nb[i];
+            if (order[nb[i]] < order[lo]) lo = nb[i];
+        }
+        up[v] = (int32_t)hi;
+        dn[v] = (int32_t)lo;
+    }
+    return ORC_OK;
+}
+
+/*
+ * Extremum labels as the fixed point the path compression of the paper
+ * converges to: desc[v] is the maximum that the chain v, up[v], up[up[v]], ...
+ * ends in, asc[v] the minimum of the dn chain.  Computed by one pass over the
+ * sorted vertex array: walking from the top, up[v] lies above v and has been
+ * labelled already, so desc[v] = desc[up[v]]; asc symmetrically from the
+ * bottom.
+ */
+int plmss_oracle_labels(const int32_t* perm, const int32_t* up, const int32_t* dn, int64_t n,
+                        int32_t* asc, int32_t* desc) {
+    if (!perm || !up || !dn || !asc || !desc || n < 1) return ORC_E_ARG;
+    for (int64_t i = n - 1; i >= 0; --i) {
+        int32_t v = perm[i];
+        desc[v] = (up[v] == v) ? v : desc[up[v]];
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t v = perm[i];
+        asc[v] = (dn[v] == v) ? v : asc[dn[v]];
+    }
+    return ORC_OK;
+}
+
+/*
+ * Morse-Smale segmentation (paper, Sec. "Morse-Smale Segmentation"): vertices
+ * with the same (minimum, maximum) pair form one region.  Regions are numbered
+ * 0..K-1 by the lexicographic order of their (asc, desc) pair.
+ */
+int plmss_oracle_ms(const int32_t* asc, const int32_t* desc, int64_t n, int32_t* ms, int64_t* k_out) {
+    if (!asc || !desc || !ms || n < 1) return ORC_E_ARG;
+    uint64_t* key = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)n);
+    if (!key) return ORC_E_NOMEM;
+    for (int64_t v = 0; v < n; ++v) key[v] = ((uint64_t)(uint32_t)asc[v] << 32) | (uint32_t)desc[v];
+    uint64_t* uniq = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)n);
+    if (!uniq) {
+        free(key);
+        return ORC_E_NOMEM;
+    }
+    memcpy(uniq, key, sizeof(uint64_t) * (size_t)n);
+    qsort(uniq, (size_t)n, sizeof(uint64_t), cmp_u64);
+    int64_t k = 0;
+    for (int64_t i = 0; i < n; ++i)
+        if (i == 0 || uniq[i] != uniq[k - 1]) uniq[k++] = uniq[i];
+    for (int64_t v = 0; v < n; ++v) {
+        int64_t lo = 0, hi = k - 1;
+        while (lo < hi) {
+            int64_t mid = (lo + hi) / 2;
+            if (uniq[mid] < key[v])
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        ms[v] = (int32_t)lo;
+    }
+    if (k_out) *k_out = k;
+    free(uniq);
+    free(key);
+    return ORC_OK;
+}
+
+/*
+ * The whole segmentation of one field: order field, steepest neighbours,
+ * extremum labels, MS ids.  Any output pointer except asc/desc/ms may be NULL.
+ * info (nullable) receives {#minima, #maxima, K}.
+ */
+int plmss_oracle_segment(const void* f, int dtype, int64_t nx, int64_t ny, int64_t nz,
+                         int32_t* order, int32_t* up, int32_t* dn, int32_t* asc, int32_t* desc,
+                         int32_t* ms, int64_t* info) {
+    grid_t g;
+    int rc = make_grid(nx, ny, nz, &g);
+    if (rc) return rc;
+    if (!f || !asc || !desc || !ms || (dtype != 0 && dtype != 1)) return ORC_E_ARG;
+    size_t bytes = sizeof(int32_t) * (size_t)g.n;
+    int32_t* o = order ? order : (int32_t*)malloc(bytes);
+    int32_t* perm = (int32_t*)malloc(bytes);
+    int32_t* u = up ? up : (int32_t*)malloc(bytes);
+    int32_t* d = dn ? dn : (int32_t*)malloc(bytes);
+    if (!o || !perm || !u || !d) {
+        rc = ORC_E_NOMEM;
+        goto done;
+    }
+    rc = plmss_oracle_order(f, dtype, nx, ny, nz, o, perm);
+    if (rc) goto done;
+    rc = plmss_oracle_steepest(o, nx, ny, nz, u, d);
+    if (rc) goto done;
+    rc = plmss_oracle_labels(perm, u, d, g.n, asc, desc);
+    if (rc) goto done;
+    int64_t k = 0;
+    rc = plmss_oracle_ms(asc, desc, g.n, ms, &k);
+    if (rc) goto done;
+    if (info) {
+        int64_t nmin = 0, nmax = 0;
+        for (int64_t v = 0; v < g.n; ++v) {
+            nmin += (asc[v] == v);
+            nmax += (desc[v] == v);
+        }
+        info[0] = nmin;
+        info[1] = nmax;
+        info[2] = k;
+    }
+done:
+    if (!order) free(o);
+    if (!up) free(u);
+    if (!dn) free(d);
+    free(perm);
+    return rc;
+}
+
+/*
+ * One vertex, straight from the definition of integral lines (paper, Sec.
+ * "Integral Lines"): step to the highest neighbour until none is higher, and
+ * to the lowest neighbour until none is lower.  "Higher" is the Simulation of
+ * Simplicity comparison on (value, index); no order field is built.  Returns
+ * the maximum and minimum reached and the number of steps of each walk.
+ */
+int plmss_oracle_trace(const void* f, int dtype, int64_t nx, int64_t ny, int64_t nz, int64_t v,
+                       int64_t* max_out, int64_t* min_out, int64_t* up_steps, int64_t* dn_steps) {
+    grid_t g;
+    int rc = make_grid(nx, ny, nz, &g);
+    if (rc) return rc;
+    if (!f || v < 0 || v >= g.n || (dtype != 0 && dtype != 1)) return ORC_E_ARG;
+    int64_t nb[14];
+    for (int dir = 0; dir < 2; ++dir) {
+        int64_t cur = v, steps = 0;
+        for (;;) {
+            double c = value(f, dtype, cur);
+            if (c != c) return ORC_E_NAN;
+            int k = neighbours(&g, cur, nb);
+            int64_t best = cur;
+            for (int i = 0; i < k; ++i) {
+                int after = sos_after(f, dtype, nb[i], best);
+                if (dir == 0 ? after : !after) best = nb[i];
+            }
+            if (best == cur) break;
+            cur = best;
+            ++steps;
+        }
+        if (dir == 0) {
+            if (max_out) *max_out = cur;
+            if (up_steps) *up_steps = steps;
+        } else {
+            if (min_out) *min_out = cur;
+            if (dn_steps) *dn_steps = steps;
+        }
+    }
+    return ORC_OK;
+}
+
+/*
+ * Path compression as the paper states it (Sec. "Ascending and Descending
+ * Segmentation", Fig. 2): L0 holds every vertex that is not its own target;
+ * each iteration replaces dsc(v) by dsc(dsc(v)) for v in L0, in place, and
+ * keeps in L1 the vertices with dsc(v) != dsc(dsc(v)) afterwards; then L0 = L1
+ * until it is empty.  Vertices are visited in increasing id order, or in
+ * decreasing order when descending != 0.  history (nullable) receives the
+ * pointer array after each iteration, at most max_hist of them.  Returns the
+ * number of iterations, or a negative status.
+ */
+int64_t plmss_oracle_compress(int32_t* dsc, int64_t n, int descending, int32_t* history,
+                              int64_t max_hist) {
+    if (!dsc || n < 1) return ORC_E_ARG;
+    for (int64_t v = 0; v < n; ++v)
+        if (dsc[v] < 0 || dsc[v] >= n) return ORC_E_ARG;
+    int32_t* list = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    if (!list) return ORC_E_NOMEM;
+    int64_t len = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t v = descending ? n - 1 - i : i;
+        if (dsc[v] != v) list[len++] = (int32_t)v;
+    }
+    int64_t iters = 0;
+    while (len > 0) {
+        int64_t next = 0;
+        for (int64_t i = 0; i < len; ++i) {
+            int32_t v = list[i];
+            dsc[v] = dsc[dsc[v]];
+            if (dsc[v] != dsc[dsc[v]]) list[next++] = v; /* still active: kept in order */
+        }
+        len = next;
+        if (history && iters < max_hist) memcpy(history + iters * n, dsc, sizeof(int32_t) * (size_t)n);
+        ++iters;
+        if (iters > 64 + n) break; /* cannot happen for a forest; guards a malformed input */
+    }
+    free(list);
+    return iters;
+}
+
+/* Sum over all vertices of the number of in-grid neighbours (= twice the edge
+ * count of the triangulation). */
+int64_t plmss_oracle_degree_sum(int64_t nx, int64_t ny, int64_t nz) {
+    grid_t g;
+    if (nx < 1 || ny < 1 || nz < 1) return ORC_E_DIMS;
+    g.nx = nx;
+    g.ny = ny;
+    g.nz = nz;
+    g.n = nx * ny * nz;
+    int64_t nb[14], s = 0;
+    for (int64_t v = 0; v < g.n; ++v) s += neighbours(&g, v, nb);
+    return s;
+}
+
+/* The neighbour ids of one vertex, for tests (nb must hold 14 entries). */
+int plmss_oracle_neighbours(int64_t nx, int64_t ny, int64_t nz, int64_t v, int64_t* nb) {
+    grid_t g;
+    int rc = make_grid(nx, ny, nz, &g);
+    if (rc) return rc;
+    if (!nb || v < 0 || v >= g.n) return ORC_E_ARG;
+    return neighbours(&g, v, nb);
+}
