@@ -1,0 +1,155 @@
+/*
+ * plmss.h -- C ABI of the MI355X (gfx950) piecewise-linear Morse-Smale
+ * segmentation library (libplmss.so).
+ *
+ * Method: Maack, Lukasczyk, Tierny, Hagen, Maciejewski, Garth, "Parallel
+ * Computation of Piecewise Linear Morse-Smale Segmentations", arXiv 2303.15491.
+ *
+ * Problem (paper, Sec. "Input Data" and "Morse-Smale Segmentation"): a scalar
+ * field f given on the vertices of a regular grid, which is implicitly cut
+ * into simplices (six tetrahedra per cube in 3-D, two triangles per square in
+ * 2-D; the cut along the (1,1,1) / (1,1) diagonal).  For every vertex v the
+ * library returns
+ *   desc[v]  the id of the maximum its steepest ascending integral line ends in,
+ *   asc[v]   the id of the minimum its steepest descending integral line ends in,
+ *   ms[v]    the id of its Morse-Smale region, i.e. of its (asc, desc) pair,
+ *   order[v] (optional) its position in the Simulation-of-Simplicity vertex
+ *            order (sorted by value, ties by vertex id; Sec. "Preprocessing").
+ *
+ * Conventions shared by every call:
+ *  - Grid dims (nx, ny, nz), each >= 1; nz == 1 is a 2-D field, ny == nz == 1
+ *    a 1-D field.  N = nx*ny*nz must be <= 2^31 - 1.  Vertex id
+ *    v = x + nx*(y + ny*z), i.e. a C-contiguous (nz, ny, nx) array.
+ *  - Neighbours of a vertex: the offsets (a,b,c) in {0,1}^3 minus (0,0,0),
+ *    and their negatives (14 in 3-D, 6 in 2-D, 2 in 1-D), clipped at the
+ *    border; no wrap-around.
+ *  - Vertex order (Sec. "Preprocessing"): u is above w iff f(u) > f(w), or
+ *    f(u) == f(w) and u > w.  IEEE comparison: -0 == +0, subnormals are
+ *    ordered exactly, +-inf are allowed.  NaN is an error (f maps into R).
+ *  - Labels are field-local int32 vertex ids.  MS ids run 0..K-1 in the
+ *    lexicographic order of the (asc, desc) pair.
+ *  - Every array argument is DEVICE memory owned by the caller unless stated
+ *    otherwise.  The library never allocates device memory; scratch space is a
+ *    caller-provided workspace of the size the matching *_workspace_bytes call
+ *    returns.
+ *  - Every call is asynchronous on `stream` (a hipStream_t; NULL = the null
+ *    stream).  The return value reports synchronous argument checks and launch
+ *    errors only.  Data-dependent errors (NaN) are written on the device to
+ *    info[0]; the labels of such a field are unspecified.
+ *  - Calls are re-entrant.  Two calls that run concurrently must not share a
+ *    workspace.
+ */
+#ifndef PLMSS_H
+#define PLMSS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes (return values, and info[0] on the device). */
+#define PLMSS_OK 0
+#define PLMSS_E_ARG (-1)       /* NULL pointer or bad enum value */
+#define PLMSS_E_DIMS (-2)      /* a dimension < 1 */
+#define PLMSS_E_TOO_LARGE (-3) /* N (or a batch's total) > 2^31 - 1 */
+#define PLMSS_E_NAN (-4)       /* the field holds a NaN (device-side) */
+#define PLMSS_E_WORKSPACE (-5) /* workspace NULL or smaller than required */
+#define PLMSS_E_HIP (-6)       /* a HIP launch or runtime call failed */
+
+/* Field element types. */
+#define PLMSS_F32 0
+#define PLMSS_F64 1
+
+typedef struct {
+    int64_t nx, ny, nz;
+} plmss_dims;
+
+/* One segmentation request. */
+typedef struct {
+    const void* field; /* device, dtype[nz][ny][nx] */
+    plmss_dims dims;
+    int32_t dtype;     /* PLMSS_F32 or PLMSS_F64 */
+    int32_t* asc;      /* device int32[N], out */
+    int32_t* desc;     /* device int32[N], out */
+    int32_t* ms;       /* device int32[N], out */
+    int32_t* order;    /* device int32[N], out; NULL = do not build the order field */
+    int32_t* info;     /* device int32[4], out, or NULL: {status, #minima, #maxima, K} */
+} plmss_job;
+
+/* Human-readable text for a status code (static storage). */
+const char* plmss_status_string(int code);
+
+/* Library version and the GPU architecture its kernels were built for. */
+const char* plmss_build_info(void);
+
+/*
+ * Full segmentation of one field (paper, Sec. "Method"): order field (only if
+ * job->order != NULL), steepest neighbours, path compression, MS ids.
+ * Workspace: plmss_workspace_bytes(dims, dtype, job->order != NULL) bytes of
+ * device memory, 256-byte aligned; its contents on entry do not matter.
+ * Returns PLMSS_OK, PLMSS_E_ARG, PLMSS_E_DIMS, PLMSS_E_TOO_LARGE,
+ * PLMSS_E_WORKSPACE or PLMSS_E_HIP.
+ */
+size_t plmss_workspace_bytes(plmss_dims dims, int32_t dtype, int32_t with_order);
+int plmss_segment(const plmss_job* job, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Step 0 alone -- the order field (paper, Sec. "Preprocessing"): sort the
+ * vertices by value with ties broken by vertex id; order[v] = position of v.
+ * A stable least-significant-digit radix sort of order-preserving integer
+ * keys.  info (nullable) receives {status, 0, 0, 0}.
+ */
+size_t plmss_order_workspace_bytes(plmss_dims dims, int32_t dtype);
+int plmss_order_field(const void* field, plmss_dims dims, int32_t dtype, int32_t* order,
+                      int32_t* info, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Step 1 alone -- steepest neighbours (paper, Sec. "Ascending and Descending
+ * Segmentation", first step): up[v] = the neighbour above all other
+ * neighbours and above v, or v itself if v is a maximum; dn[v] likewise
+ * downwards.  If order != NULL it is used as the vertex order (int32[N], a
+ * permutation of 0..N-1); otherwise the order is taken from field/dtype with
+ * the tie rule above.  info (nullable) receives {status, #minima, #maxima, 0}.
+ * Needs no workspace.
+ */
+int plmss_steepest(const void* field, const int32_t* order, plmss_dims dims, int32_t dtype,
+                   int32_t* up, int32_t* dn, int32_t* info, void* stream);
+
+/*
+ * Step 2 alone -- path compression (paper, same section, second step):
+ * repeats p(v) <- p(p(v)) until p(p(v)) == p(v), in place, on both pointer
+ * arrays.  On entry desc = up and asc = dn from step 1 (any forest whose roots
+ * point to themselves is accepted); on return desc[v] is the root of v's up
+ * chain and asc[v] the root of its dn chain.  n = N.  No workspace.
+ */
+int plmss_compress(int32_t* desc, int32_t* asc, int64_t n, void* stream);
+
+/*
+ * Step 3 alone -- Morse-Smale ids (paper, Sec. "Morse-Smale Segmentation"):
+ * ms[v] = rank of (asc[v], desc[v]) among the distinct pairs of the field, in
+ * lexicographic order; info (nullable) receives {status, 0, 0, K}.  n = N;
+ * labels must lie in [0, n).
+ */
+size_t plmss_ms_workspace_bytes(int64_t n);
+int plmss_ms_ids(const int32_t* asc, const int32_t* desc, int64_t n, int32_t* ms, int32_t* info,
+                 void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Many fields of different sizes in one pass: the same results as calling
+ * plmss_segment on each job, computed by one launch per step over all fields
+ * together.  jobs is a HOST array of n_jobs entries; the sum of their N must
+ * be <= 2^31 - 1.  Order fields are not built in a batch (jobs[i].order must
+ * be NULL).  One field's NaN only sets that job's info[0].
+ * Workspace: plmss_batch_workspace_bytes(n_jobs, jobs) bytes.
+ */
+size_t plmss_batch_workspace_bytes(int32_t n_jobs, const plmss_job* jobs);
+int plmss_segment_batch(int32_t n_jobs, const plmss_job* jobs, void* workspace,
+                        size_t workspace_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PLMSS_H */

@@ -1,0 +1,280 @@
+"""MI355X (gfx950) piecewise-linear Morse-Smale segmentation.
+
+Python binding of ``libplmss.so`` (C ABI in ``include/plmss.h``).  This module
+only marshals arguments: torch provides device memory and the current HIP
+stream, every step of the segmentation runs in the library's HIP kernels.
+There is no CPU fallback; without the built library every call raises.
+
+Method: Maack et al., "Parallel Computation of Piecewise Linear Morse-Smale
+Segmentations", arXiv 2303.15491, Sec. "Method".
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = ["PlmssError", "library", "segment", "order_field", "steepest", "compress", "ms_ids",
+           "segment_batch", "workspace_bytes", "batch_workspace_bytes"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libplmss.so")
+
+OK, E_ARG, E_DIMS, E_TOO_LARGE, E_NAN, E_WORKSPACE, E_HIP = 0, -1, -2, -3, -4, -5, -6
+F32, F64 = 0, 1
+
+
+class PlmssError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        msg = _lib_status(code)
+        super().__init__(f"{what}: {msg} (status {code})" if what else f"{msg} (status {code})")
+        self.code = code
+
+
+class Dims(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64)]
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("field", ctypes.c_void_p), ("dims", Dims), ("dtype", ctypes.c_int32),
+                ("asc", ctypes.c_void_p), ("desc", ctypes.c_void_p), ("ms", ctypes.c_void_p),
+                ("order", ctypes.c_void_p), ("info", ctypes.c_void_p)]
+
+
+_lib = None
+
+_SIGNATURES = {
+    "plmss_status_string": ([ctypes.c_int], ctypes.c_char_p),
+    "plmss_build_info": ([], ctypes.c_char_p),
+    "plmss_workspace_bytes": ([Dims, ctypes.c_int32, ctypes.c_int32], ctypes.c_size_t),
+    "plmss_segment": ([ctypes.POINTER(Job), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
+    "plmss_order_workspace_bytes": ([Dims, ctypes.c_int32], ctypes.c_size_t),
+    "plmss_order_field": ([ctypes.c_void_p, Dims, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                           ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
+    "plmss_steepest": ([ctypes.c_void_p, ctypes.c_void_p, Dims, ctypes.c_int32, ctypes.c_void_p,
+                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "plmss_compress": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p], ctypes.c_int),
+    "plmss_ms_workspace_bytes": ([ctypes.c_int64], ctypes.c_size_t),
+    "plmss_ms_ids": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                      ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
+    "plmss_batch_workspace_bytes": ([ctypes.c_int32, ctypes.POINTER(Job)], ctypes.c_size_t),
+    "plmss_segment_batch": ([ctypes.c_int32, ctypes.POINTER(Job), ctypes.c_void_p, ctypes.c_size_t,
+                             ctypes.c_void_p], ctypes.c_int),
+}
+
+
+def library():
+    """The loaded ``libplmss.so``; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise PlmssError(E_HIP, f"{LIB_PATH} is missing; build it with "
+                                    "`python -m paper_2303_15491_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = lib
+    return _lib
+
+
+def _lib_status(code: int) -> str:
+    try:
+        return library().plmss_status_string(code).decode()
+    except Exception:  # the library itself may be what is missing
+        return "status"
+
+
+def _check(rc: int, what: str):
+    if rc != OK:
+        raise PlmssError(rc, what)
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def dims_of(shape) -> Dims:
+    """Grid dims of an (nz, ny, nx), (ny, nx) or (nx,) shaped field."""
+    shape = tuple(int(s) for s in shape)
+    if len(shape) == 1:
+        return Dims(shape[0], 1, 1)
+    if len(shape) == 2:
+        return Dims(shape[1], shape[0], 1)
+    if len(shape) == 3:
+        return Dims(shape[2], shape[1], shape[0])
+    raise ValueError("a field must be 1-, 2- or 3-dimensional")
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.float64:
+        return F64
+    raise TypeError("field must be float32 or float64")
+
+
+def _field_check(field):
+    if not field.is_cuda:
+        raise ValueError("field must be a device tensor")
+    if not field.is_contiguous():
+        raise ValueError("field must be C-contiguous")
+    return _dtype_code(field)
+
+
+def _stream(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _workspace(nbytes: int, device, workspace=None):
+    torch = _torch()
+    if workspace is not None:
+        if workspace.numel() * workspace.element_size() < nbytes:
+            raise PlmssError(E_WORKSPACE, "workspace")
+        return workspace
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def workspace_bytes(shape, dtype=None, with_order: bool = False) -> int:
+    torch = _torch()
+    code = F64 if dtype == torch.float64 else F32
+    return int(library().plmss_workspace_bytes(dims_of(shape), code, int(with_order)))
+
+
+def segment(field, with_order: bool = False, workspace=None, stream=None, out=None):
+    """Morse-Smale segmentation of one device field.
+
+    Returns a dict of int32 device tensors of the field's shape: ``asc``,
+    ``desc``, ``ms`` (and ``order`` when ``with_order``), plus ``info``, an
+    int32 device tensor {status, #minima, #maxima, K}.  Asynchronous on the
+    current stream; read ``info`` to learn K or a NaN error.
+    """
+    torch = _torch()
+    code = _field_check(field)
+    dims = dims_of(field.shape)
+    dev = field.device
+    if out is None:
+        out = {k: torch.empty(field.shape, dtype=torch.int32, device=dev) for k in ("asc", "desc", "ms")}
+        if with_order:
+            out["order"] = torch.empty(field.shape, dtype=torch.int32, device=dev)
+        out["info"] = torch.empty(4, dtype=torch.int32, device=dev)
+    lib = library()
+    ws = _workspace(lib.plmss_workspace_bytes(dims, code, int(with_order)), dev, workspace)
+    job = Job(field.data_ptr(), dims, code, out["asc"].data_ptr(), out["desc"].data_ptr(),
+              out["ms"].data_ptr(), out["order"].data_ptr() if out.get("order") is not None else None,
+              out["info"].data_ptr())
+    _check(lib.plmss_segment(ctypes.byref(job), _ptr(ws), ws.numel(), _stream(stream)), "plmss_segment")
+    return out
+
+
+def order_field(field, workspace=None, stream=None):
+    """Simulation-of-Simplicity order field (int32 device tensor) and info."""
+    torch = _torch()
+    code = _field_check(field)
+    dims = dims_of(field.shape)
+    lib = library()
+    order = torch.empty(field.shape, dtype=torch.int32, device=field.device)
+    info = torch.empty(4, dtype=torch.int32, device=field.device)
+    ws = _workspace(lib.plmss_order_workspace_bytes(dims, code), field.device, workspace)
+    _check(lib.plmss_order_field(_ptr(field), dims, code, _ptr(order), _ptr(info), _ptr(ws), ws.numel(),
+                                 _stream(stream)), "plmss_order_field")
+    return order, info
+
+
+def steepest(field=None, order=None, stream=None):
+    """Steepest ascending/descending neighbours (up, dn, info) from a float
+    field or from a materialised order field."""
+    torch = _torch()
+    src = order if order is not None else field
+    if src is None:
+        raise ValueError("need a field or an order field")
+    if not src.is_cuda or not src.is_contiguous():
+        raise ValueError("input must be a contiguous device tensor")
+    code = F32
+    if order is None:
+        code = _field_check(field)
+    elif order.dtype != torch.int32:
+        raise TypeError("order must be int32")
+    up = torch.empty(src.shape, dtype=torch.int32, device=src.device)
+    dn = torch.empty(src.shape, dtype=torch.int32, device=src.device)
+    info = torch.empty(4, dtype=torch.int32, device=src.device)
+    _check(library().plmss_steepest(_ptr(field) if order is None else None, _ptr(order), dims_of(src.shape), code,
+                                    _ptr(up), _ptr(dn), _ptr(info), _stream(stream)), "plmss_steepest")
+    return up, dn, info
+
+
+def compress(desc, asc, stream=None):
+    """Path compression in place: on entry up/dn pointers, on return labels."""
+    torch = _torch()
+    for t in (desc, asc):
+        if not t.is_cuda or not t.is_contiguous() or t.dtype != torch.int32:
+            raise ValueError("pointer arrays must be contiguous int32 device tensors")
+    if desc.numel() != asc.numel():
+        raise ValueError("size mismatch")
+    _check(library().plmss_compress(_ptr(desc), _ptr(asc), desc.numel(), _stream(stream)), "plmss_compress")
+    return desc, asc
+
+
+def ms_ids(asc, desc, workspace=None, stream=None):
+    """MS region ids (int32 device tensor) and info from asc/desc labels."""
+    torch = _torch()
+    for t in (desc, asc):
+        if not t.is_cuda or not t.is_contiguous() or t.dtype != torch.int32:
+            raise ValueError("label arrays must be contiguous int32 device tensors")
+    n = asc.numel()
+    lib = library()
+    ms = torch.empty(asc.shape, dtype=torch.int32, device=asc.device)
+    info = torch.empty(4, dtype=torch.int32, device=asc.device)
+    ws = _workspace(lib.plmss_ms_workspace_bytes(n), asc.device, workspace)
+    _check(lib.plmss_ms_ids(_ptr(asc), _ptr(desc), n, _ptr(ms), _ptr(info), _ptr(ws), ws.numel(),
+                            _stream(stream)), "plmss_ms_ids")
+    return ms, info
+
+
+def _jobs(fields, outs):
+    arr = (Job * len(fields))()
+    for i, (f, o) in enumerate(zip(fields, outs)):
+        arr[i] = Job(f.data_ptr(), dims_of(f.shape), _dtype_code(f), o["asc"].data_ptr(), o["desc"].data_ptr(),
+                     o["ms"].data_ptr(), None, o["info"].data_ptr())
+    return arr
+
+
+def batch_workspace_bytes(fields) -> int:
+    torch = _torch()
+    dummy = [{k: torch.empty(0, dtype=torch.int32) for k in ("asc", "desc", "ms", "info")} for _ in fields]
+    arr = (Job * len(fields))()
+    for i, f in enumerate(fields):
+        arr[i] = Job(1, dims_of(f.shape), _dtype_code(f), 1, 1, 1, None, None)
+    del dummy
+    return int(library().plmss_batch_workspace_bytes(len(fields), arr))
+
+
+def segment_batch(fields, workspace=None, stream=None, outs=None):
+    """Segment many device fields of any sizes in one pass; returns one dict
+    per field as :func:`segment` does (without ``order``)."""
+    torch = _torch()
+    for f in fields:
+        _field_check(f)
+    if outs is None:
+        outs = []
+        for f in fields:
+            o = {k: torch.empty(f.shape, dtype=torch.int32, device=f.device) for k in ("asc", "desc", "ms")}
+            o["info"] = torch.empty(4, dtype=torch.int32, device=f.device)
+            outs.append(o)
+    arr = _jobs(fields, outs)
+    lib = library()
+    nbytes = lib.plmss_batch_workspace_bytes(len(fields), arr)
+    if nbytes == 0:
+        raise PlmssError(E_ARG, "plmss_batch_workspace_bytes")
+    ws = _workspace(nbytes, fields[0].device, workspace)
+    _check(lib.plmss_segment_batch(len(fields), arr, _ptr(ws), ws.numel(), _stream(stream)), "plmss_segment_batch")
+    return outs

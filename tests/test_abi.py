@@ -1,0 +1,95 @@
+"""The C-ABI library loads, exports every declared entry point and rejects bad
+arguments synchronously (no GPU needed: the checks run before any HIP call)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2303_15491_amd as plmss
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "plmss.h")) as fh:
+        text = fh.read()
+    return sorted(set(re.findall(r"\b(plmss_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_entry_points():
+    names = _declared()
+    for n in ("plmss_segment", "plmss_workspace_bytes", "plmss_order_field", "plmss_steepest",
+              "plmss_compress", "plmss_ms_ids", "plmss_segment_batch", "plmss_status_string"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = plmss.library()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert b"gfx950" in lib.plmss_build_info()
+
+
+def test_status_strings():
+    lib = plmss.library()
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        s = lib.plmss_status_string(code).decode()
+        assert s and s != "unknown status"
+    assert lib.plmss_status_string(42).decode() == "unknown status"
+
+
+FAKE = 0x1000  # never dereferenced: every case below fails its checks first
+
+
+def _job(nx, ny, nz, dtype=plmss.F32, field=FAKE, asc=FAKE):
+    return plmss.Job(field, plmss.Dims(nx, ny, nz), dtype, asc, FAKE, FAKE, None, None)
+
+
+def test_segment_argument_errors():
+    lib = plmss.library()
+    seg = lib.plmss_segment
+    assert seg(None, None, 0, None) == plmss.E_ARG
+    assert seg(ctypes.byref(_job(4, 4, 1, field=None)), None, 0, None) == plmss.E_ARG
+    assert seg(ctypes.byref(_job(4, 4, 1, asc=None)), None, 0, None) == plmss.E_ARG
+    assert seg(ctypes.byref(_job(4, 4, 1, dtype=7)), None, 0, None) == plmss.E_ARG
+    assert seg(ctypes.byref(_job(0, 4, 1)), None, 0, None) == plmss.E_DIMS
+    assert seg(ctypes.byref(_job(4, -1, 1)), None, 0, None) == plmss.E_DIMS
+    assert seg(ctypes.byref(_job(2048, 2048, 512)), None, 0, None) == plmss.E_TOO_LARGE
+    assert seg(ctypes.byref(_job(2**31, 1, 1)), None, 0, None) == plmss.E_TOO_LARGE
+    need = lib.plmss_workspace_bytes(plmss.Dims(4, 4, 1), plmss.F32, 0)
+    assert seg(ctypes.byref(_job(4, 4, 1)), None, need, None) == plmss.E_WORKSPACE
+    assert seg(ctypes.byref(_job(4, 4, 1)), ctypes.c_void_p(FAKE), need - 1, None) == plmss.E_WORKSPACE
+    assert seg(ctypes.byref(_job(4, 4, 1)), ctypes.c_void_p(FAKE + 4), need, None) == plmss.E_WORKSPACE
+
+
+def test_step_entry_point_argument_errors():
+    lib = plmss.library()
+    d = plmss.Dims(8, 8, 8)
+    assert lib.plmss_order_field(None, d, 0, FAKE, None, FAKE, 1 << 30, None) == plmss.E_ARG
+    assert lib.plmss_order_field(FAKE, plmss.Dims(0, 1, 1), 0, FAKE, None, FAKE, 1 << 30, None) == plmss.E_DIMS
+    assert lib.plmss_order_field(FAKE, d, 0, FAKE, None, FAKE, 16, None) == plmss.E_WORKSPACE
+    assert lib.plmss_steepest(None, None, d, 0, FAKE, FAKE, None, None) == plmss.E_ARG
+    assert lib.plmss_steepest(FAKE, None, d, 3, FAKE, FAKE, None, None) == plmss.E_ARG
+    assert lib.plmss_steepest(FAKE, None, plmss.Dims(1, 0, 1), 0, FAKE, FAKE, None, None) == plmss.E_DIMS
+    assert lib.plmss_compress(None, FAKE, 10, None) == plmss.E_ARG
+    assert lib.plmss_compress(FAKE, FAKE, 0, None) == plmss.E_DIMS
+    assert lib.plmss_compress(FAKE, FAKE, 2**31, None) == plmss.E_TOO_LARGE
+    assert lib.plmss_ms_ids(FAKE, FAKE, 0, FAKE, None, FAKE, 1 << 30, None) == plmss.E_DIMS
+    assert lib.plmss_ms_ids(FAKE, FAKE, 100, FAKE, None, FAKE, 8, None) == plmss.E_WORKSPACE
+
+
+def test_workspace_sizes():
+    lib = plmss.library()
+    small = lib.plmss_workspace_bytes(plmss.Dims(64, 64, 1), plmss.F32, 0)
+    big = lib.plmss_workspace_bytes(plmss.Dims(512, 512, 512), plmss.F32, 1)
+    assert 0 < small < big
+    assert big < 40 * 512**3  # about 28 bytes per vertex plus fixed tables
+    assert lib.plmss_workspace_bytes(plmss.Dims(0, 1, 1), plmss.F32, 0) == 0
+    assert lib.plmss_ms_workspace_bytes(0) == 0
+
+
+def test_python_binding_refuses_host_tensors():
+    torch = pytest.importorskip("torch")
+    with pytest.raises(ValueError):
+        plmss.segment(torch.zeros(4, 4))

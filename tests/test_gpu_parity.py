@@ -1,0 +1,199 @@
+"""GPU parity: the HIP library, called through its C ABI, against the CPU
+oracle on the same seeded inputs.  Labels are integers, so the bar is
+bit-exact equality of every output (asc, desc, ms, order, #minima, #maxima, K).
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2303_15491_amd as plmss
+from paper_2303_15491_amd import fields
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    return _t
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _host(t):
+    return t.cpu().numpy()
+
+
+def _compare_full(torch, f, with_order=False, label=""):
+    _say(f"segment {label} shape={f.shape} dtype={f.dtype} order={with_order}")
+    ref = oracle.segment(f)
+    out = plmss.segment(_dev(torch, f), with_order=with_order)
+    torch.cuda.synchronize()
+    info = _host(out["info"])
+    assert info[0] == 0
+    for k in ("asc", "desc", "ms"):
+        np.testing.assert_array_equal(_host(out[k]), ref[k], err_msg=f"{label} {k}")
+    if with_order:
+        np.testing.assert_array_equal(_host(out["order"]), ref["order"], err_msg=f"{label} order")
+    assert (info[1], info[2], info[3]) == (ref["n_min"], ref["n_max"], ref["K"]), label
+    return ref, out
+
+
+def test_fig1_worked_example(torch):
+    with open(os.path.join(GOLDEN, "fig1_wallmodes.json")) as fh:
+        g = json.load(fh)
+    f = np.array(g["field"], np.float32).reshape(4, 4)
+    _say("fig1")
+    out = plmss.segment(_dev(torch, f), with_order=True)
+    torch.cuda.synchronize()
+    assert _host(out["asc"]).ravel().tolist() == g["asc"]
+    assert _host(out["desc"]).ravel().tolist() == g["desc"]
+    assert _host(out["ms"]).ravel().tolist() == g["ms"]
+    assert _host(out["order"]).ravel().tolist() == g["field"]
+    assert _host(out["info"]).tolist() == [0, 2, 2, g["K"]]
+
+
+@pytest.mark.parametrize("with_order", [False, True])
+def test_config_2d_gaussian_mix(torch, with_order):
+    _compare_full(torch, fields.workload_c1(), with_order, "c1")
+
+
+@pytest.mark.parametrize("shape", [(37, 70, 130), (16, 8, 64), (17, 9, 65), (3, 200, 7), (40, 1, 33), (5, 77, 1),
+                                   (1, 300, 257)])
+def test_ragged_tiles_both_paths(torch, shape):
+    f = fields.smoothed_noise(shape, 1.5, seed=sum(shape))
+    _, a = _compare_full(torch, f, False, f"ragged{shape}")
+    _, b = _compare_full(torch, f, True, f"ragged{shape}+order")
+    for k in ("asc", "desc", "ms"):
+        assert torch.equal(a[k], b[k])
+
+
+def test_degenerate_dims(torch):
+    _compare_full(torch, np.arange(1000, dtype=np.float32), True, "line")
+    _compare_full(torch, np.array([1.5], np.float32), True, "single")
+    _compare_full(torch, np.array([2.0, 1.0], np.float32), True, "pair")
+    _compare_full(torch, fields.smoothed_noise((50, 60), 2.0, 7).reshape(1, 50, 60), False, "nz1")
+    _compare_full(torch, np.full((7, 9, 11), 3.0, np.float32), True, "constant")
+
+
+def test_ties_signed_zero_subnormal_infinity(torch):
+    rng = np.random.default_rng(12)
+    tiny = np.float32(1.4e-45)
+    vals = np.array([0.0, -0.0, tiny, -tiny, 2 * tiny, np.inf, -np.inf, 1.0, -1.0, 0.5], np.float32)
+    _compare_full(torch, rng.choice(vals, size=(19, 23, 70)), True, "specials")
+    _compare_full(torch, rng.integers(0, 4, size=(33, 66, 67)).astype(np.float32), True, "ties")
+    _compare_full(torch, rng.choice(vals, size=(19, 23, 70)).astype(np.float64), True, "specials-f64")
+
+
+def test_float64_widened_is_identical(torch):
+    f = fields.smoothed_noise((24, 40, 70), 1.5, 9)
+    _, a = _compare_full(torch, f, True, "f32")
+    _, b = _compare_full(torch, f.astype(np.float64), True, "f64")
+    for k in ("asc", "desc", "ms", "order"):
+        assert torch.equal(a[k], b[k])
+
+
+def test_nan_reported_on_device(torch):
+    f = fields.smoothed_noise((8, 9, 10), 1.5, 3)
+    f[3, 4, 5] = np.nan
+    _say("nan")
+    for with_order in (False, True):
+        out = plmss.segment(_dev(torch, f), with_order=with_order)
+        torch.cuda.synchronize()
+        assert int(out["info"][0]) == plmss.E_NAN
+
+
+def test_step_entry_points_match_oracle(torch):
+    f = fields.smoothed_noise((21, 35, 90), 1.5, 13)
+    ref = oracle.segment(f)
+    _say("order_field")
+    order, info = plmss.order_field(_dev(torch, f))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(_host(order), ref["order"])
+    assert int(info[0]) == 0
+    _say("steepest from field")
+    up, dn, info = plmss.steepest(field=_dev(torch, f))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(_host(up), ref["up"])
+    np.testing.assert_array_equal(_host(dn), ref["dn"])
+    assert (int(info[1]), int(info[2])) == (ref["n_min"], ref["n_max"])
+    _say("steepest from order")
+    up2, dn2, _ = plmss.steepest(order=_dev(torch, ref["order"]))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(_host(up2), ref["up"])
+    np.testing.assert_array_equal(_host(dn2), ref["dn"])
+    _say("compress")
+    d, a = plmss.compress(_dev(torch, ref["up"]), _dev(torch, ref["dn"]))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(_host(d), ref["desc"])
+    np.testing.assert_array_equal(_host(a), ref["asc"])
+    _say("ms_ids")
+    ms, info = plmss.ms_ids(_dev(torch, ref["asc"]), _dev(torch, ref["desc"]))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(_host(ms), ref["ms"])
+    assert int(info[3]) == ref["K"]
+
+
+def test_compress_long_chain(torch):
+    n = 1 << 20
+    up = np.minimum(np.arange(n, dtype=np.int32) + 1, n - 1)
+    _say("compress chain")
+    d, a = plmss.compress(_dev(torch, up), _dev(torch, np.arange(n, dtype=np.int32)))
+    torch.cuda.synchronize()
+    assert (_host(d) == n - 1).all() and (_host(a) == np.arange(n)).all()
+
+
+def test_config_3d_256_full_oracle(torch):
+    f = fields.workload_c2(256)
+    _compare_full(torch, f, False, "c2-256")
+
+
+def test_config_3d_512_sampled(torch):
+    _say("c3-512 generate")
+    f = fields.workload_c3(512)
+    n = f.size
+    _say("c3-512 segment")
+    out = plmss.segment(_dev(torch, f), with_order=True)
+    torch.cuda.synchronize()
+    info = _host(out["info"])
+    asc, desc, ms, order = (_host(out[k]).ravel() for k in ("asc", "desc", "ms", "order"))
+    assert info[0] == 0
+    _say("c3-512 checks")
+    rng = np.random.default_rng(99)
+    flat = f.ravel()
+    for v in rng.integers(0, n, 300):
+        mx, mn, _, _ = oracle.trace(f, int(v))
+        assert (mx, mn) == (desc[v], asc[v]), v
+    # order: a permutation that sorts (value, id)
+    assert np.bincount(order, minlength=n).max() == 1
+    sample = np.unique(rng.integers(0, n, 200000))
+    s = sample[np.argsort(order[sample], kind="stable")]
+    fv = flat[s]
+    assert ((fv[1:] > fv[:-1]) | ((fv[1:] == fv[:-1]) & (s[1:] > s[:-1]))).all()
+    # labels are extrema of the right kind and fixed points
+    assert (asc[asc] == asc).all() and (desc[desc] == desc).all()
+    assert int((desc == np.arange(n)).sum()) == info[2] and int((asc == np.arange(n)).sum()) == info[1]
+    # ms: lexicographic rank of the pair
+    pair = asc.astype(np.int64) * n + desc
+    ps = pair[sample]
+    o = np.argsort(ps, kind="stable")
+    ps, ms_s = ps[o], ms[sample][o]
+    assert ((ms_s[1:] > ms_s[:-1]) == (ps[1:] > ps[:-1])).all()
+    assert (ms_s[1:] >= ms_s[:-1]).all()
+    assert ms.min() == 0 and ms.max() == info[3] - 1
+    assert len(np.unique(pair)) == info[3]
