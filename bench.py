@@ -1,0 +1,237 @@
+"""Throughput of the Morse-Smale segmentation on one MI355X.
+
+One step = one full segmentation of one field: order field (radix sort),
+steepest neighbours, path compression, MS ids -- every step of the method,
+with the input already resident in HBM.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--workload c3|c2|c1|c3f64]
+
+Single GPU only: ``--gpus`` above 1 exits with a message.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mvertices/s full MS segmentation (bit-exact), batched vs plain; p99 ms"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic HBM bytes per vertex of each kernel kind: every array the step
+# is defined on is read once and written once (float32 field, int32 labels).
+#   steepest : read order or f (4), write up, dn (8)
+#   jump     : read up, dn (8), write asc, desc (8)
+#   ms_final : read slot (4), write ms (4)
+ALGO_BYTES = {"steepest": 12.0, "jump": 16.0, "ms_final": 8.0}
+# One radix pass of (key, id) pairs reads and writes both (16 B); the first
+# pass reads only the field (4 + 8), the last writes only order[id] (8 + 4).
+RADIX_PASS_BYTES = 16.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def workload(name: str):
+    from paper_2303_15491_amd import fields
+
+    if name == "c1":
+        return fields.workload_c1(), "2D 64x64 float32 sum of 8 Gaussians + U(-0.01,0.01) noise (seed 1)"
+    if name == "c2":
+        return fields.workload_c2(256), "3D 256^3 float32 N(0,1) smoothed sigma=3 + 0.1 z-ramp (seed 2)"
+    if name == "c3":
+        return fields.workload_c3(512), "3D 512^3 float32 N(0,1) smoothed sigma=1.5 (seed 3)"
+    if name == "c3f64":
+        return fields.workload_c3(512).astype(np.float64), "3D 512^3 float64 (widened float32) N(0,1) smoothed sigma=1.5 (seed 3)"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_info():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def timed_region(step, steps, torch, lib=None, trace=None, max_launches=0):
+    """Runs `steps` steps between two device synchronisations; returns the wall
+    time in ms and (if traced) the per-launch (kind, ms) list."""
+    torch.cuda.synchronize()
+    if trace is not None:
+        lib.plmss_trace_begin(trace)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    launches = []
+    if trace is not None:
+        lib.plmss_trace_end(trace)
+        kinds = (ctypes.c_int32 * max_launches)()
+        ms = (ctypes.c_float * max_launches)()
+        m = lib.plmss_trace_read(trace, kinds, ms, max_launches)
+        if m < 0:
+            raise RuntimeError(f"trace read failed: {m}")
+        launches = [(lib.plmss_kernel_name(kinds[i]).decode(), ms[i]) for i in range(m)]
+    return (t1 - t0) * 1e3, launches
+
+
+def per_kernel(launches, steps):
+    agg = {}
+    for name, ms in launches:
+        a = agg.setdefault(name, {"launches": 0, "total_ms": 0.0})
+        a["launches"] += 1
+        a["total_ms"] += ms
+    for a in agg.values():
+        a["ms_per_step"] = a["total_ms"] / steps
+        a["avg_launch_ms"] = a["total_ms"] / a["launches"]
+    return agg
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--cpu-slab", type=int, default=128,
+                    help="planes of the field the CPU oracle segments for the baseline (0 = skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the segmentation of one field runs on one device)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2303_15491_amd as plmss
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    lib = plmss.library()
+    log(f"generating workload {args.workload}")
+    f_host, desc = workload(args.workload)
+    n = int(f_host.size)
+    dev = torch.device("cuda:0")
+    field = torch.from_numpy(f_host).to(dev)
+    dims = plmss.dims_of(field.shape)
+    code = plmss.F64 if field.dtype == torch.float64 else plmss.F32
+    outs = {k: torch.empty(field.shape, dtype=torch.int32, device=dev) for k in ("asc", "desc", "ms", "order")}
+    outs["info"] = torch.zeros(4, dtype=torch.int32, device=dev)
+    ws_bytes = lib.plmss_workspace_bytes(dims, code, 1)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def make_job(with_order):
+        return plmss.Job(field.data_ptr(), dims, code, outs["asc"].data_ptr(), outs["desc"].data_ptr(),
+                         outs["ms"].data_ptr(), outs["order"].data_ptr() if with_order else None,
+                         outs["info"].data_ptr())
+
+    job_full, job_labels = make_job(True), make_job(False)
+
+    def step_full():
+        rc = lib.plmss_segment(ctypes.byref(job_full), ctypes.c_void_p(ws.data_ptr()), ws_bytes, stream)
+        if rc:
+            raise plmss.PlmssError(rc, "plmss_segment")
+
+    def step_labels():
+        rc = lib.plmss_segment(ctypes.byref(job_labels), ctypes.c_void_p(ws.data_ptr()), ws_bytes, stream)
+        if rc:
+            raise plmss.PlmssError(rc, "plmss_segment")
+
+    max_launches = 128 * max(args.steps, 1)
+    trace = lib.plmss_trace_create(max_launches)
+    if not trace:
+        raise RuntimeError("plmss_trace_create failed")
+
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step_full()
+        step_labels()
+    torch.cuda.synchronize()
+    info = outs["info"].cpu().tolist()
+    if info[0] != 0:
+        raise RuntimeError(f"device status {info[0]}")
+
+    log(f"timing {args.steps} full steps")
+    wall_full, launches = timed_region(step_full, args.steps, torch, lib, trace, max_launches)
+    log(f"timing {args.steps} label-only steps")
+    wall_labels, launches_l = timed_region(step_labels, args.steps, torch, lib, trace, max_launches)
+    lib.plmss_trace_destroy(trace)
+
+    ms_step = wall_full / args.steps
+    value = n / (ms_step * 1e-3) / 1e6
+    ms_step_l = wall_labels / args.steps
+    kern = per_kernel(launches, args.steps)
+    kern_l = per_kernel(launches_l, args.steps)
+
+    # roofline of the dominant kernel of the full step
+    dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
+    avg_ms = kern[dom]["avg_launch_ms"]
+    if dom in ALGO_BYTES:
+        per_launch_bytes = ALGO_BYTES[dom] * n
+        basis = f"{ALGO_BYTES[dom]:g} B/vertex x {n} vertices"
+    elif dom == "radix_scatter":
+        per_launch_bytes = RADIX_PASS_BYTES * n
+        basis = f"{RADIX_PASS_BYTES:g} B/vertex x {n} vertices (one radix pass)"
+    else:
+        per_launch_bytes = None
+        basis = "n/a"
+    achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9 if per_launch_bytes else None
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": per_launch_bytes, "basis": basis}
+
+    # CPU baseline: the oracle on a bounded slab of the same field, one core
+    cpu = None
+    if args.cpu_slab > 0:
+        import oracle
+
+        sl = f_host[: args.cpu_slab] if f_host.ndim == 3 else f_host
+        log(f"cpu baseline on {sl.shape}")
+        t0 = time.perf_counter()
+        oracle.segment(np.ascontiguousarray(sl))
+        t1 = time.perf_counter()
+        model, ncpu = cpu_info()
+        cpu = {"value": sl.size / (t1 - t0) / 1e6, "unit": "Mvertices/s", "cores": 1, "kind": "oracle",
+               "sample": f"serial C oracle (order field, steepest, labels, MS ids) on the first "
+                         f"{sl.shape[0] if sl.ndim == 3 else 1} planes {tuple(sl.shape)} of the same field, "
+                         f"{t1 - t0:.2f} s", "host_cpu": model, "host_nproc": ncpu}
+
+    labels_value = n / (ms_step_l * 1e-3) / 1e6
+    out = {
+        "metric": METRIC, "value": value, "unit": "Mvertices/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": desc, "n_vertices": n, "field_dtype": str(f_host.dtype), "order_field": True,
+                   "parallelism": "single-gpu"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "path_frac_of_hbm_roofline": n * 48.0 / (ms_step * 1e-3) / (HBM_PEAK_GBS * 1e9),
+        "labels_only": {"value": labels_value, "ms_per_step": ms_step_l,
+                        "path_frac_of_hbm_roofline": n * 48.0 / (ms_step_l * 1e-3) / (HBM_PEAK_GBS * 1e9),
+                        "note": "same labels, order field not materialised (vertex order compared in place)"},
+        "kernels_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in sorted(kern.items())},
+        "kernels_ms_per_step_labels_only": {k: round(v["ms_per_step"], 4) for k, v in sorted(kern_l.items())},
+        "paper_context": "PLMSS Asc/Desc+MS on Miranda 512^3 (a different, simplified field): 57.6 Mvertices/s "
+                         "on 24 Xeon SP 6126 cores, 3.36 on 1 core (Table 2)",
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

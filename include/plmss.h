@@ -57,6 +57,7 @@ extern "C" {
 #define PLMSS_E_NAN (-4)       /* the field holds a NaN (device-side) */
 #define PLMSS_E_WORKSPACE (-5) /* workspace NULL or smaller than required */
 #define PLMSS_E_HIP (-6)       /* a HIP launch or runtime call failed */
+#define PLMSS_E_NOCONV (-7)    /* path compression hit its iteration cap (device-side) */
 
 /* Field element types. */
 #define PLMSS_F32 0
@@ -147,6 +148,37 @@ int plmss_ms_ids(const int32_t* asc, const int32_t* desc, int64_t n, int32_t* ms
 size_t plmss_batch_workspace_bytes(int32_t n_jobs, const plmss_job* jobs);
 int plmss_segment_batch(int32_t n_jobs, const plmss_job* jobs, void* workspace,
                         size_t workspace_bytes, void* stream);
+
+/*
+ * Launch tracing, for measurement.  While a trace is active on the calling
+ * host thread (between plmss_trace_begin and plmss_trace_end), every kernel
+ * launch made by the calls above is bracketed by two hipEvents recorded on the
+ * launch's own stream; the work done is unchanged.  plmss_trace_read waits for
+ * the recorded events and returns, per launch, its kernel kind and its
+ * duration in milliseconds.  A trace records at most max_launches launches;
+ * later ones run untraced.  Handles are host objects; create returns NULL on
+ * failure; the other calls return PLMSS_OK, PLMSS_E_ARG or PLMSS_E_HIP
+ * (read returns the number of launches copied, or a negative status).
+ */
+#define PLMSS_KERNEL_MISC 0          /* small setup / bookkeeping kernels */
+#define PLMSS_KERNEL_RADIX_HIST 1    /* radix sort: per-worker digit counts */
+#define PLMSS_KERNEL_RADIX_SCAN 2    /* radix sort: digit offsets */
+#define PLMSS_KERNEL_RADIX_SCATTER 3 /* radix sort: stable scatter (order field, pair sort) */
+#define PLMSS_KERNEL_STEEPEST 4      /* steepest neighbours */
+#define PLMSS_KERNEL_JUMP 5          /* path compression (+ MS pair listing) */
+#define PLMSS_KERNEL_PREFIX 6        /* prefix sums */
+#define PLMSS_KERNEL_COMPACT 7       /* MS pair compaction */
+#define PLMSS_KERNEL_RANK 8          /* MS pair ranking */
+#define PLMSS_KERNEL_MS_FINAL 9      /* MS id write-back */
+#define PLMSS_KERNEL_KINDS 10
+
+typedef struct plmss_trace plmss_trace;
+plmss_trace* plmss_trace_create(int32_t max_launches);
+void plmss_trace_destroy(plmss_trace* trace);
+int plmss_trace_begin(plmss_trace* trace);
+int plmss_trace_end(plmss_trace* trace);
+int32_t plmss_trace_read(plmss_trace* trace, int32_t* kinds, float* ms, int32_t max);
+const char* plmss_kernel_name(int32_t kind);
 
 #ifdef __cplusplus
 }

@@ -59,6 +59,13 @@ _SIGNATURES = {
     "plmss_batch_workspace_bytes": ([ctypes.c_int32, ctypes.POINTER(Job)], ctypes.c_size_t),
     "plmss_segment_batch": ([ctypes.c_int32, ctypes.POINTER(Job), ctypes.c_void_p, ctypes.c_size_t,
                              ctypes.c_void_p], ctypes.c_int),
+    "plmss_trace_create": ([ctypes.c_int32], ctypes.c_void_p),
+    "plmss_trace_destroy": ([ctypes.c_void_p], None),
+    "plmss_trace_begin": ([ctypes.c_void_p], ctypes.c_int),
+    "plmss_trace_end": ([ctypes.c_void_p], ctypes.c_int),
+    "plmss_trace_read": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float),
+                          ctypes.c_int32], ctypes.c_int32),
+    "plmss_kernel_name": ([ctypes.c_int32], ctypes.c_char_p),
 }
 
 

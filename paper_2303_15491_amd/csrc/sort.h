@@ -1,13 +1,15 @@
 // Stable least-significant-digit radix sort and device-wide prefix sums.
 //
-// Layout: a fixed grid of kWorkers blocks; worker b owns one contiguous slice
-// of the input (whole tiles of kTile keys), so every pass is
+// Every pass is three launches over the same grid of "workers" (blocks); worker
+// b owns one contiguous slice of whole kTile-key tiles:
 //   hist    : per-worker digit counts            -> hist[digit][worker]
 //   scan    : exclusive scan of each digit's row -> hist (in place), dtotal
-//   scatter : stable rank inside the worker's slice, write to
+//   scatter : stable rank inside each tile, staged through LDS so that each
+//             digit's run leaves the block as one contiguous write, at
 //             digit base + hist[digit][worker] + rank
-// The element count may live in device memory (count_ptr), so a sort whose
-// length is only known on the device needs no host round trip.
+// With a host-known length the grid has one worker per tile.  The length may
+// instead live in device memory (count_ptr) with a fixed grid, so a sort whose
+// size only the device knows needs no host round trip.
 #pragma once
 
 #include "common.h"
@@ -16,9 +18,9 @@ namespace plmss {
 
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;  // == kBlock: one thread per digit
-constexpr int kWorkers = 1024;
 constexpr int kItems = 16;               // keys per thread per tile
 constexpr int kTile = kBlock * kItems;
+constexpr int kWorkers = 1024;           // grid of device-sized sorts and scans
 static_assert(kRadix == kBlock, "one thread per digit");
 
 __device__ __forceinline__ uint32_t load_count(const uint32_t* count_ptr, uint32_t n) {
@@ -102,6 +104,7 @@ template <class Src, bool CHECK_NAN>
 __global__ __launch_bounds__(kBlock) void k_radix_hist(Src src, const uint32_t* count_ptr,
                                                        uint32_t n, int shift, uint32_t* hist,
                                                        int32_t* info) {
+    using K = typename Src::key_t;
     __shared__ uint32_t h[kWavesPerBlock][kRadix];
     __shared__ int nan_seen;
     const int t = threadIdx.x, w = wave_id();
@@ -112,9 +115,19 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(Src src, const uint32_t* 
     uint32_t lo, hi;
     worker_range(load_count(count_ptr, n), blockIdx.x, gridDim.x, kTile, &lo, &hi);
     bool bad = false;
-    for (uint32_t i = lo + t; i < hi; i += kBlock) {
-        atomicAdd(&h[w][digit_of(src.key(i), shift)], 1u);
-        if (CHECK_NAN) bad |= src.nan(i);
+    for (uint32_t tile = lo; tile < hi; tile += kTile) {
+        K key[kItems];
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            const uint32_t idx = tile + uint32_t(i) * kBlock + t;
+            key[i] = idx < hi ? src.key(idx) : K(0);
+            if (CHECK_NAN && idx < hi) bad |= src.nan(idx);
+        }
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            const uint32_t idx = tile + uint32_t(i) * kBlock + t;
+            if (idx < hi) atomicAdd(&h[w][digit_of(key[i], shift)], 1u);
+        }
     }
     if (CHECK_NAN && bad) nan_seen = 1;
     __syncthreads();
@@ -131,22 +144,35 @@ __global__ __launch_bounds__(kBlock) void k_radix_digit_scan(uint32_t* hist, uin
                                                              int workers) {
     __shared__ uint32_t tmp[kWavesPerBlock];
     uint32_t* row = hist + size_t(blockIdx.x) * workers;
-    const int per = (workers + kBlock - 1) / kBlock;
-    const int beg = threadIdx.x * per;
-    uint32_t s = 0;
-    for (int i = 0; i < per; ++i)
-        if (beg + i < workers) s += row[beg + i];
-    uint32_t tot;
-    uint32_t run = block_exclusive_scan(s, tmp, &tot);
-    for (int i = 0; i < per; ++i) {
-        if (beg + i < workers) {
-            const uint32_t c = row[beg + i];
-            row[beg + i] = run;
-            run += c;
+    uint32_t run = 0;
+    for (int base = 0; base < workers; base += kBlock * 4) {
+        // four consecutive entries per thread per round, loads issued together
+        const int beg = base + threadIdx.x * 4;
+        uint32_t c[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) c[i] = (beg + i < workers) ? row[beg + i] : 0u;
+        uint32_t tot;
+        uint32_t e = run + block_exclusive_scan(c[0] + c[1] + c[2] + c[3], tmp, &tot);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (beg + i < workers) row[beg + i] = e;
+            e += c[i];
         }
+        run += tot;
     }
-    if (threadIdx.x == 0) dtotal[blockIdx.x] = tot;
+    if (threadIdx.x == 0) dtotal[blockIdx.x] = run;
 }
+
+template <typename K>
+struct ScatterSmem {
+    K keys[kTile];
+    uint32_t vals[kTile];
+    uint32_t wcnt[kWavesPerBlock][kRadix];
+    uint32_t run[kRadix];
+    uint32_t tstart[kRadix];
+    uint32_t tcount[kRadix];
+    uint32_t tmp[kWavesPerBlock];
+};
 
 template <class Src, class Dst>
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(Src src, Dst dst,
@@ -154,69 +180,103 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(Src src, Dst dst,
                                                           int shift, const uint32_t* hist,
                                                           const uint32_t* dtotal) {
     using K = typename Src::key_t;
-    __shared__ uint32_t run[kRadix];
-    __shared__ uint32_t wcnt[kWavesPerBlock][kRadix];
-    __shared__ uint32_t tmp[kWavesPerBlock];
+    __shared__ ScatterSmem<K> sm;
     const int t = threadIdx.x, w = wave_id(), lane = lane_id();
     uint32_t tot;
-    const uint32_t base = block_exclusive_scan(dtotal[t], tmp, &tot);
-    run[t] = base + hist[size_t(t) * gridDim.x + blockIdx.x];
+    const uint32_t base = block_exclusive_scan(dtotal[t], sm.tmp, &tot);
+    sm.run[t] = base + hist[size_t(t) * gridDim.x + blockIdx.x];
     uint32_t lo, hi;
     worker_range(load_count(count_ptr, n), blockIdx.x, gridDim.x, kTile, &lo, &hi);
     const uint64_t lt = lanemask_lt();
     for (uint32_t tile = lo; tile < hi; tile += kTile) {
+        const uint32_t tsize = min(uint32_t(kTile), hi - tile);
 #pragma unroll
-        for (int i = 0; i < kWavesPerBlock; ++i) wcnt[i][t] = 0;
-        __syncthreads();
+        for (int i = 0; i < kWavesPerBlock; ++i) sm.wcnt[i][t] = 0;
+        // wave w owns keys [w*64*kItems, (w+1)*64*kItems) of the tile, row i of
+        // the wave holds 64 consecutive keys: (w, i, lane) is the input order
         K key[kItems];
-        uint32_t val[kItems], dig[kItems], local[kItems];
+        uint32_t val[kItems];
         const uint32_t wbase = tile + uint32_t(w) * kWave * kItems + lane;
 #pragma unroll
         for (int i = 0; i < kItems; ++i) {
             const uint32_t idx = wbase + uint32_t(i) * kWave;
+            key[i] = idx < hi ? src.key(idx) : K(0);
+            val[i] = idx < hi ? src.val(idx) : 0u;
+        }
+        __syncthreads();
+        uint32_t local[kItems];
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            const uint32_t idx = wbase + uint32_t(i) * kWave;
             const bool valid = idx < hi;
-            key[i] = valid ? src.key(idx) : K(0);
-            val[i] = valid ? src.val(idx) : 0u;
-            dig[i] = valid ? digit_of(key[i], shift) : 0u;
-            const uint64_t peers = match_digit(dig[i], valid);
+            const uint32_t d = digit_of(key[i], shift);
+            const uint64_t peers = match_digit(d, valid);
             uint32_t prior = 0;
-            if (valid) prior = wcnt[w][dig[i]];
+            if (valid) prior = sm.wcnt[w][d];
             local[i] = prior + uint32_t(__popcll(peers & lt));
             // the highest peer lane publishes the new count for this digit
-            if (valid && (peers >> lane) == 1ull) wcnt[w][dig[i]] = prior + uint32_t(__popcll(peers));
+            if (valid && (peers >> lane) == 1ull) sm.wcnt[w][d] = prior + uint32_t(__popcll(peers));
         }
         __syncthreads();
         {
-            uint32_t acc = run[t];
+            uint32_t c[kWavesPerBlock], sum = 0;
 #pragma unroll
             for (int i = 0; i < kWavesPerBlock; ++i) {
-                const uint32_t c = wcnt[i][t];
-                wcnt[i][t] = acc;
-                acc += c;
+                c[i] = sm.wcnt[i][t];
+                sum += c[i];
             }
-            run[t] = acc;
+            uint32_t ttot;
+            uint32_t acc = block_exclusive_scan(sum, sm.tmp, &ttot);
+            sm.tstart[t] = acc;
+            sm.tcount[t] = sum;
+#pragma unroll
+            for (int i = 0; i < kWavesPerBlock; ++i) {
+                sm.wcnt[i][t] = acc;
+                acc += c[i];
+            }
         }
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < kItems; ++i) {
             const uint32_t idx = wbase + uint32_t(i) * kWave;
-            if (idx < hi) dst.put(wcnt[w][dig[i]] + local[i], key[i], val[i]);
+            if (idx < hi) {
+                const uint32_t p = sm.wcnt[w][digit_of(key[i], shift)] + local[i];
+                sm.keys[p] = key[i];
+                sm.vals[p] = val[i];
+            }
         }
         __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            const uint32_t j = uint32_t(i) * kBlock + t;
+            if (j < tsize) {
+                const K k = sm.keys[j];
+                const uint32_t d = digit_of(k, shift);
+                dst.put(sm.run[d] + (j - sm.tstart[d]), k, sm.vals[j]);
+            }
+        }
+        __syncthreads();
+        sm.run[t] += sm.tcount[t];
     }
 }
 
 // ---- device-wide exclusive prefix sums over uint32 ---------------------------------
 
-// partial[b] = sum of in[lo..hi) over worker b's slice.
+// partial[b] = sum of in[lo..hi) over worker b's slice (slices of kTile).
 __global__ __launch_bounds__(kBlock) void k_sum_reduce(const uint32_t* in,
                                                        const uint32_t* count_ptr, uint32_t n,
                                                        uint32_t* partial) {
     __shared__ uint32_t tmp[kWavesPerBlock];
     uint32_t lo, hi;
-    worker_range(load_count(count_ptr, n), blockIdx.x, gridDim.x, kBlock, &lo, &hi);
+    worker_range(load_count(count_ptr, n), blockIdx.x, gridDim.x, kTile, &lo, &hi);
     uint32_t s = 0;
-    for (uint32_t i = lo + threadIdx.x; i < hi; i += kBlock) s += in[i];
+    for (uint32_t tile = lo; tile < hi; tile += kTile) {
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            const uint32_t idx = tile + uint32_t(i) * kBlock + threadIdx.x;
+            s += idx < hi ? in[idx] : 0u;
+        }
+    }
     uint32_t tot;
     block_exclusive_scan(s, tmp, &tot);
     if (threadIdx.x == 0) partial[blockIdx.x] = tot;
@@ -241,6 +301,34 @@ __global__ __launch_bounds__(kBlock) void k_scan_partials(uint32_t* partial, int
         }
     }
     if (threadIdx.x == 0 && total) *total = tot;
+}
+
+// out[i] = exclusive prefix of in[] (worker slices of kTile, offsets from
+// partial[]).  Each thread sums kItems consecutive entries.
+__global__ __launch_bounds__(kBlock) void k_scan_apply(const uint32_t* in, const uint32_t* count_ptr,
+                                                       uint32_t n, const uint32_t* partial,
+                                                       uint32_t* out) {
+    __shared__ uint32_t tmp[kWavesPerBlock];
+    uint32_t lo, hi;
+    worker_range(load_count(count_ptr, n), blockIdx.x, gridDim.x, kTile, &lo, &hi);
+    uint32_t run = partial[blockIdx.x];
+    for (uint32_t tile = lo; tile < hi; tile += kTile) {
+        const uint32_t beg = tile + threadIdx.x * kItems;
+        uint32_t c[kItems], s = 0;
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            c[i] = beg + i < hi ? in[beg + i] : 0u;
+            s += c[i];
+        }
+        uint32_t tot;
+        uint32_t e = run + block_exclusive_scan(s, tmp, &tot);
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            if (beg + i < hi) out[beg + i] = e;
+            e += c[i];
+        }
+        run += tot;
+    }
 }
 
 }  // namespace plmss
