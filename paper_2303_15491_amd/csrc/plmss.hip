@@ -263,7 +263,7 @@ void launch_chase(const ChasePlan& cp, const plmss_dims& d, uint32_t* U, uint32_
 }
 
 // Tile shape of the neighbour scan: kTX x TY columns over ZC planes (3-D), or
-// kTX x 32 squares (2-D and 1-D fields).
+// kTX x 16 rectangles (2-D and 1-D fields).
 template <bool RESOLVE, class Src>
 void launch_steepest(Src src, const plmss_dims& d, uint32_t* up, uint32_t* dn, int32_t* info,
                      hipStream_t s) {
@@ -272,7 +272,7 @@ void launch_steepest(Src src, const plmss_dims& d, uint32_t* up, uint32_t* dn, i
         if (d.nz > 1)
             k_steepest<Src, 8, 16, RESOLVE><<<steepest_blocks(g, 8, 16), kBlock, 0, s>>>(src, g, up, dn, info);
         else
-            k_steepest<Src, 32, 1, RESOLVE><<<steepest_blocks(g, 32, 1), kBlock, 0, s>>>(src, g, up, dn, info);
+            k_steepest<Src, 16, 1, RESOLVE><<<steepest_blocks(g, 16, 1), kBlock, 0, s>>>(src, g, up, dn, info);
     });
 }
 

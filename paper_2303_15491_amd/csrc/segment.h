@@ -23,12 +23,13 @@ struct FieldOrder {
     }
 };
 
-// A materialised order field (distinct ranks).
+// A materialised order field (distinct ranks), as rank + 1 so that key 0 stays
+// below every vertex (it marks grid positions outside the field).
 struct RankOrder {
     using key_t = uint32_t;
     static constexpr bool kCheckNan = false;
     const int32_t* order;
-    __device__ __forceinline__ uint32_t load(size_t i, bool&) const { return uint32_t(order[i]); }
+    __device__ __forceinline__ uint32_t load(size_t i, bool&) const { return uint32_t(order[i]) + 1u; }
 };
 
 struct GridDims {
@@ -94,35 +95,61 @@ __device__ __forceinline__ void steepest_codes(const typename Src::key_t (*pl)[P
 
 constexpr uint32_t kMark = 0x80000000u;     // "this label is an extremum" in a resolved pointer
 constexpr uint32_t kMaxHops = 1u << 24;     // iteration cap of the pointer-chasing loops
-constexpr uint32_t kExit = 0x8000u;      // local pointer: the target lies outside the tile
+constexpr uint32_t kExit = 0x8000u;
+constexpr int kResolveRounds = 3;           // in-tile jumping sweeps      // local pointer: the target lies outside the tile
 
 // Steepest neighbours of every vertex.
 //
 // A block owns a kTX x TY column of the grid over ZC consecutive planes and
-// marches through them, keeping planes z-1, z, z+1 (with a one-vertex halo) in
-// LDS, so the field is read from HBM about once.
+// marches through them, so the field is read from HBM about once.  Positions
+// outside the grid hold key 0, below every vertex.
+//
+// Search (32-bit keys): the candidate set of v -- its 14 neighbours and v --
+// is the union of four 2x2 squares: at (x-1, y-1) in planes z-1 and z, and at
+// (x, y) in planes z and z+1, listed here in increasing vertex-id order
+// (within a square: (0,0) (1,0) (0,1) (1,1)).  Each square's maximum and
+// minimum is found once per plane and shared by the four vertices that use
+// it; a vertex combines four squares.  ">=" for the maximum and "<" for the
+// minimum, in id order, break equal keys by vertex id as the paper's order
+// does.  64-bit keys (float64 fields) use the plain 15-candidate scan.
 //
 // RESOLVE == false: up[v] / dn[v] = the steepest ascending / descending
 //   neighbour (v itself at a maximum / minimum).
 // RESOLVE == true: the paper's path compression is run inside the tile first.
 //   Every vertex keeps, in LDS, a pointer to its steepest neighbour if that
-//   lies in the tile (or an exit mark with the direction if it does not); the
-//   pointers are compressed in place, p <- p[p], until each points at a root
-//   of the tile: a true extremum or an exit vertex.  The result written is
+//   lies in the tile, or an exit mark with the direction if it does not; the
+//   pointers are then compressed in place, p <- p[p], round by round, until
+//   each points at the end of its tile chain.  The result written is
 //     up[v] = kMark | maximum           if v's ascending chain ends in the tile,
 //     up[v] = first vertex outside      otherwise (a pointer still to follow);
 //   likewise dn[v].
 // info[1] += #minima, info[2] += #maxima; info[0] = PLMSS_E_NAN on a NaN.
+template <typename K, int TY>
+struct SquarePlanes {
+    K mx[3][TY + 1][kTX + 1];  // square maxima
+    K mn[3][TY + 1][kTX + 1];  // square minima of (key - 1): key 0 becomes the largest
+    uint8_t tag[3][TY + 1][kTX + 1];  // winner positions: max in bits 0-1, min in bits 2-3
+};
+
 template <class Src, int TY, int ZC, bool RESOLVE>
 __global__ __launch_bounds__(kBlock) void k_steepest(Src src, GridDims g, uint32_t* up,
                                                      uint32_t* dn, int32_t* info) {
     using K = typename Src::key_t;
+    constexpr bool kSquares = sizeof(K) == 4;
     constexpr int PX = kTX + 2, PY = TY + 2, RPW = TY / kWavesPerBlock;
     constexpr int TV = RESOLVE ? kTX * TY * ZC : 1;
+    constexpr int kLoads = (PY * PX + kBlock - 1) / kBlock;
+    constexpr int kSq = (TY + 1) * (kTX + 1);
+    constexpr int kSqLoops = (kSq + kBlock - 1) / kBlock;
     static_assert(TY % kWavesPerBlock == 0, "rows per wave");
+    static_assert((TY & (TY - 1)) == 0, "power-of-two rows");
     static_assert(kTX * TY * ZC < int(kExit), "local indices need 15 bits");
-    __shared__ K pl[3][PY][PX];
+    // raw key planes: the ring of three for the plain scan, one staging plane
+    // for the square search
+    __shared__ K pl[kSquares ? 1 : 3][PY][PX];
+    __shared__ SquarePlanes<K, kSquares ? TY : 0> sq;
     __shared__ uint32_t lp[TV];  // local pointers: up in the low half, dn in the high half
+    __shared__ int32_t off_tab[16];  // vertex-id offset of each neighbour code
     __shared__ uint32_t cnt_min, cnt_max;
     __shared__ int nan_seen;
     const int t = threadIdx.x, w = wave_id(), lane = lane_id();
@@ -140,26 +167,98 @@ __global__ __launch_bounds__(kBlock) void k_steepest(Src src, GridDims g, uint32
         cnt_max = 0;
         nan_seen = 0;
     }
+    if (t < 16) off_tab[t] = t < 15 ? code_offset(t, g.nx, S) : 0;
+    // this thread's share of a plane load: LDS slot and in-plane offset, the
+    // same for every plane
+    int ld_slot[kLoads];
+    int64_t ld_off[kLoads];
+#pragma unroll
+    for (int k = 0; k < kLoads; ++k) {
+        const int i = t + k * kBlock;
+        const int r = i / PX, c = i - r * PX;
+        const int gx = x0 - 1 + c, gy = y0 - 1 + r;
+        const bool in = i < PY * PX && gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny;
+        ld_slot[k] = i < PY * PX ? i : -1;
+        ld_off[k] = in ? int64_t(gy) * int64_t(sx) + gx : -1;
+    }
     bool nan = false;
+    // plane loads go through registers so that the next plane's loads are in
+    // flight while the current plane is computed
+    K pre[kLoads];
+    auto fetch_plane = [&](int z) {
+        const size_t zb = size_t(z) * sxy;
+#pragma unroll
+        for (int k = 0; k < kLoads; ++k)
+            pre[k] = ld_off[k] >= 0 ? src.load(zb + size_t(ld_off[k]), nan) : K(0);
+    };
+    auto store_plane = [&](int slot) {
+        K* dst = &pl[kSquares ? 0 : slot][0][0];
+#pragma unroll
+        for (int k = 0; k < kLoads; ++k)
+            if (ld_slot[k] >= 0) dst[ld_slot[k]] = pre[k];
+    };
     auto load_plane = [&](int slot, int z) {
-        for (int i = t; i < PY * PX; i += kBlock) {
-            const int r = i / PX, c = i - r * PX;
-            const int gx = x0 - 1 + c, gy = y0 - 1 + r;
-            K k = K(0);
-            if (gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny)
-                k = src.load(size_t(z) * sxy + size_t(gy) * sx + size_t(gx), nan);
-            pl[slot][r][c] = k;
+        fetch_plane(z);
+        store_plane(slot);
+    };
+    // square results of one plane (z valid) or of a missing plane
+    auto squares = [&](int slot, bool exists) {
+        if constexpr (kSquares) {
+#pragma unroll
+            for (int k = 0; k < kSqLoops; ++k) {
+                const int i = t + k * kBlock;
+                if (i >= kSq) break;
+                const int r = i / (kTX + 1), c = i - r * (kTX + 1);
+                K hi = K(0), lo = ~K(0);
+                uint32_t th = 0, tl = 0;
+                if (exists) {
+                    const K a[4] = {pl[0][r][c], pl[0][r][c + 1], pl[0][r + 1][c], pl[0][r + 1][c + 1]};
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const bool gh = a[q] >= hi;
+                        hi = gh ? a[q] : hi;
+                        th = gh ? uint32_t(q) : th;
+                        const K am = a[q] - K(1);
+                        const bool gl = am < lo;
+                        lo = gl ? am : lo;
+                        tl = gl ? uint32_t(q) : tl;
+                    }
+                }
+                sq.mx[slot][r][c] = hi;
+                sq.mn[slot][r][c] = lo;
+                sq.tag[slot][r][c] = uint8_t(th | (tl << 2));
+            }
         }
     };
     int pm = 0, pc = 1, pn = 2;
-    if (z0 > 0) load_plane(pm, z0 - 1);
+    if (z0 > 0) {
+        load_plane(pm, z0 - 1);
+        if (kSquares) {
+            __syncthreads();
+            squares(pm, true);
+        }
+    } else if (kSquares) {
+        squares(pm, false);
+    }
+    if (kSquares) __syncthreads();
     load_plane(pc, z0);
+    if (kSquares) {
+        __syncthreads();
+        squares(pc, true);
+    }
+    if (z0 + 1 < g.nz) fetch_plane(z0 + 1);
     const int x = x0 + lane;
     const bool xm = x > 0, xp = x < g.nx - 1;
     uint32_t my_min = 0, my_max = 0;
     for (int z = z0; z < z1; ++z) {
-        if (z + 1 < g.nz) load_plane(pn, z + 1);
+        __syncthreads();  // the previous plane's readers are done: its buffers are free
+        if (z + 1 < g.nz) store_plane(pn);  // plane z + 1, fetched one step ahead
+        if (kSquares) {
+            __syncthreads();
+            squares(pn, z + 1 < g.nz);
+        }
         __syncthreads();
+        if (z + 2 < g.nz && z + 1 < z1) fetch_plane(z + 2);
         const bool zm = z > 0, zp = z < g.nz - 1;
         const bool interior = x0 > 0 && x0 + kTX < g.nx && y0 > 0 && y0 + TY < g.ny && zm && zp;
         const int lz = z - z0;
@@ -167,12 +266,34 @@ __global__ __launch_bounds__(kBlock) void k_steepest(Src src, GridDims g, uint32
         for (int r = 0; r < RPW; ++r) {
             const int ly = w * RPW + r, y = y0 + ly;
             const bool inside = x < g.nx && y < g.ny;
-            const bool ym = y > 0, yp = y < g.ny - 1;
             int cu, cd;
-            if (interior)
-                steepest_codes<Src, PY, false>(pl, pm, pc, pn, lane, ly, xm, xp, ym, yp, zm, zp, cu, cd);
-            else
-                steepest_codes<Src, PY, true>(pl, pm, pc, pn, lane, ly, xm, xp, ym, yp, zm, zp, cu, cd);
+            if constexpr (kSquares) {
+                // squares k = 0..3 in id order; code = base_k + winner position
+                const int sl[4] = {pm, pc, pc, pn};
+                const int rr[4] = {ly, ly, ly + 1, ly + 1};
+                const int cc[4] = {lane, lane, lane + 1, lane + 1};
+                const int base[4] = {0, 4, 7, 11};
+                K bu = K(0), bd = ~K(0);
+                cu = kSelf;
+                cd = kSelf;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const K h = sq.mx[sl[k]][rr[k]][cc[k]];
+                    const K l = sq.mn[sl[k]][rr[k]][cc[k]];
+                    const uint32_t tg = sq.tag[sl[k]][rr[k]][cc[k]];
+                    const bool gu = h >= bu, gd = l < bd;
+                    bu = gu ? h : bu;
+                    cu = gu ? base[k] + int(tg & 3u) : cu;
+                    bd = gd ? l : bd;
+                    cd = gd ? base[k] + int(tg >> 2) : cd;
+                }
+            } else {
+                const bool ym = y > 0, yp = y < g.ny - 1;
+                if (interior)
+                    steepest_codes<Src, PY, false>(pl, pm, pc, pn, lane, ly, xm, xp, ym, yp, zm, zp, cu, cd);
+                else
+                    steepest_codes<Src, PY, true>(pl, pm, pc, pn, lane, ly, xm, xp, ym, yp, zm, zp, cu, cd);
+            }
             if (inside) {
                 my_max += (cu == kSelf);
                 my_min += (cd == kSelf);
@@ -186,82 +307,98 @@ __global__ __launch_bounds__(kBlock) void k_steepest(Src src, GridDims g, uint32
             } else {
                 const int li = (lz * TY + ly) * kTX + lane;
                 auto local = [&](int c) -> uint32_t {
-                    if (!inside) return uint32_t(li);  // padding: a harmless root
-                    const int d = c - kSelf, m = d < 0 ? -d : d, s = d < 0 ? -1 : 1;
-                    const int ax = lane + s * (m & 1), ay = ly + s * ((m >> 1) & 1),
-                              az = lz + s * ((m >> 2) & 1);
-                    if (ax < 0 || ax >= kTX || ay < 0 || ay >= TY || az < 0 || az >= ZC)
-                        return kExit | uint32_t(c);
-                    return uint32_t((az * TY + ay) * kTX + ax);
+                    const int d = c - kSelf, m = d < 0 ? -d : d;
+                    const int dx = (m & 1), dy = (m >> 1) & 1, dz = (m >> 2) & 1;
+                    const int ax = d < 0 ? lane - dx : lane + dx, ay = d < 0 ? ly - dy : ly + dy,
+                              az = d < 0 ? lz - dz : lz + dz;
+                    const bool in = uint32_t(ax) < uint32_t(kTX) && uint32_t(ay) < uint32_t(TY) &&
+                                    uint32_t(az) < uint32_t(ZC);
+                    return !inside ? uint32_t(li)  // padding: a harmless root
+                                   : in ? uint32_t((az * TY + ay) * kTX + ax) : (kExit | uint32_t(c));
                 };
                 lp[li] = local(cu) | (local(cd) << 16);
             }
         }
-        __syncthreads();
         const int tmp = pm;
         pm = pc;
         pc = pn;
         pn = tmp;
     }
     if (RESOLVE) {
-        // tile-local rows of the last chunk may be missing (z1 - z0 < ZC)
-        for (int lz = z1 - z0; lz < ZC; ++lz)
-            for (int r = 0; r < RPW; ++r) {
-                const int li = (lz * TY + w * RPW + r) * kTX + lane;
-                lp[li] = uint32_t(li) | (uint32_t(li) << 16);
-            }
         __syncthreads();
-        // in-place pointer jumping over the tile; a pointer whose target is
-        // an exit vertex (kExit mark) or a root stays put
-        for (int round = 0; round < 16; ++round) {
-            bool changed = false;
-            for (int i = t; i < TV; i += kBlock) {
-                const uint32_t e = lp[i];
-                uint32_t pu = e & 0xffffu, pd = e >> 16;
-                bool ch = false;
-                if (!(pu & kExit)) {
-                    const uint32_t q = lp[pu] & 0xffffu;
-                    if (!(q & kExit) && q != pu) {
-                        pu = q;
-                        ch = true;
-                    }
-                }
-                if (!(pd & kExit)) {
-                    const uint32_t q = lp[pd] >> 16;
-                    if (!(q & kExit) && q != pd) {
-                        pd = q;
-                        ch = true;
-                    }
-                }
-                if (ch) lp[i] = pu | (pd << 16);
-                changed |= ch;
-            }
-            if (!__syncthreads_or(changed)) break;
+        // entries of this thread: (lz, row) pairs over the tile's planes; entry
+        // e has local index li0 + (e / RPW) * TY * kTX + (e % RPW) * kTX
+        constexpr int kMine = ZC * RPW;
+        static_assert(kMine <= 32, "one mask bit per entry");
+        const int nz_t = z1 - z0;
+        const int li0 = (w * RPW) * kTX + lane;
+        uint32_t todo = 0;
+#pragma unroll
+        for (int e = 0; e < kMine; ++e) {
+            const int lz = e / RPW, ly = w * RPW + e % RPW;
+            if (lz < nz_t && x < g.nx && y0 + ly < g.ny) todo |= 1u << e;
         }
-        // write-out: the root of the tile chain, resolved or to be followed
-        const size_t tile0 = size_t(z0) * sxy + size_t(y0) * sx + size_t(x0);
-        auto gid = [&](uint32_t li) -> int32_t {
-            const int ax = int(li % kTX), ay = int((li / kTX) % TY), az = int(li / (kTX * TY));
-            return int32_t(tile0 + size_t(az) * sxy + size_t(ay) * sx + size_t(ax));
+        // in-place rounds of p <- p[p]; an entry is finished once both of its
+        // pointers reach an exit vertex or a root.  The loop over entries is
+        // uniform; an entry no lane of the wave still needs is skipped.
+        auto step = [&](int e, bool& ch) {
+            const bool mine = (todo >> e) & 1u;
+            if (!__ballot(mine)) return;
+            const int li = li0 + (e / RPW) * (TY * kTX) + (e % RPW) * kTX;
+            const uint32_t own = lp[li];
+            const uint32_t pu = own & 0xffffu, pd = own >> 16;
+            const uint32_t qu = lp[pu & (kExit - 1)] & 0xffffu, qd = lp[pd & (kExit - 1)] >> 16;
+            const bool su = ((pu | qu) & kExit) || qu == pu;  // cannot move
+            const bool sd = ((pd | qd) & kExit) || qd == pd;
+            const uint32_t nu = (mine && !su) ? qu : pu, nd = (mine && !sd) ? qd : pd;
+            // an entry has one owner, so rewriting an unchanged value is harmless
+            lp[li] = nu | (nd << 16);
+            ch |= (nu != pu) || (nd != pd);
+            todo &= (su && sd) ? ~(1u << e) : ~0u;
         };
-        for (int lz = 0; lz < z1 - z0; ++lz) {
+        // sweeps alternate direction, so chains of either orientation compress
+        // in one sweep when their entries happen to lie in sweep order.  A few
+        // sweeps finish almost every tile chain; what is left is written as an
+        // unfinished pointer, which the chase kernel follows.
+        for (int round = 0; round < kResolveRounds; ++round) {
+            bool ch = false;
+            if (round & 1) {
+#pragma unroll
+                for (int e = kMine - 1; e >= 0; --e) step(e, ch);
+            } else {
+#pragma unroll
+                for (int e = 0; e < kMine; ++e) step(e, ch);
+            }
+            if (!__syncthreads_or(ch)) break;
+        }
+        // write-out: the end of the tile chain, resolved or to be followed.
+        // Vertex ids fit in 32 bits.
+        const uint32_t tile0 = uint32_t(z0) * uint32_t(S) + uint32_t(y0) * uint32_t(g.nx) + uint32_t(x0);
+        auto gid = [&](uint32_t li) -> uint32_t {
+            const uint32_t ax = li & (kTX - 1), ay = (li / kTX) & (TY - 1), az = li / (kTX * TY);
+            return tile0 + az * uint32_t(S) + ay * uint32_t(g.nx) + ax;
+        };
+        // p: the vertex's pointer; q: the pointer of p's vertex; v: the vertex
+        auto resolve = [&](uint32_t v, uint32_t p, uint32_t q) -> uint32_t {
+            const bool own_exit = p & kExit;
+            const uint32_t base = own_exit ? v : gid(p);
+            const uint32_t code = (own_exit ? p : q) & 0xffu;
+            const uint32_t ext = base + uint32_t(off_tab[code & 15u]);
+            if (own_exit || (q & kExit)) return ext;  // leaves the tile
+            return q == p ? (kMark | base) : base;     // an extremum, or still to follow
+        };
+        for (int lz = 0; lz < nz_t; ++lz) {
 #pragma unroll
             for (int r = 0; r < RPW; ++r) {
                 const int ly = w * RPW + r, y = y0 + ly;
                 if (x >= g.nx || y >= g.ny) continue;
                 const uint32_t li = uint32_t((lz * TY + ly) * kTX + lane);
-                const uint32_t e = lp[li];
-                auto resolve = [&](uint32_t p, int half) -> uint32_t {
-                    if (p & kExit)  // v itself is an exit vertex
-                        return uint32_t(gid(li) + code_offset(int(p & 0xffu), g.nx, S));
-                    const uint32_t q = (lp[p] >> half) & 0xffffu;
-                    if (q == p) return kMark | uint32_t(gid(p));  // an extremum
-                    if (q & kExit) return uint32_t(gid(p) + code_offset(int(q & 0xffu), g.nx, S));
-                    return uint32_t(gid(p));  // not fully compressed: follow later
-                };
-                const size_t v = size_t(z0 + lz) * sxy + size_t(y) * sx + size_t(x);
-                up[v] = resolve(e & 0xffffu, 0);
-                dn[v] = resolve(e >> 16, 16);
+                const uint32_t v = tile0 + uint32_t(lz) * uint32_t(S) + uint32_t(ly) * uint32_t(g.nx) + uint32_t(lane);
+                const uint32_t own = lp[li];
+                const uint32_t pu = own & 0xffffu, pd = own >> 16;
+                const uint32_t qu = lp[pu & (kExit - 1)] & 0xffffu, qd = lp[pd & (kExit - 1)] >> 16;
+                up[v] = resolve(v, pu, qu);
+                dn[v] = resolve(v, pd, qd);
             }
         }
     }
@@ -294,7 +431,7 @@ inline int steepest_blocks(const GridDims& g, int ty, int zc) {
 // so a 3-D tile lists far fewer pairs than a row of the same size would.
 constexpr int kJV = 2048;            // vertices per tile
 constexpr int kJPer = kJV / kBlock;  // per thread
-constexpr int kHash = 2 * kJV;       // hash slots: never more than half full
+constexpr int kHash = kJV;           // hash slots: a tile has at most kJV distinct pairs
 constexpr uint64_t kEmpty = ~0ull;   // pair keys are < 2^62
 
 template <int JX, int JY, int JZ>
@@ -355,7 +492,8 @@ __global__ __launch_bounds__(kBlock) void k_chase(uint32_t* U, uint32_t* D, Grid
         // a pointer leads strictly up (down) its chain, so the hops end; the
         // cap only guards against a malformed input
         // the eight vertices of a thread advance together, so their gathers
-        // are in flight at the same time
+        // are in flight at the same time; from the second hop on, a pointer
+        // is written back so that later readers of the vertex jump further
         bool pending = true;
         uint32_t hops = 0;
         while (pending && hops < kMaxHops) {
@@ -364,12 +502,12 @@ __global__ __launch_bounds__(kBlock) void k_chase(uint32_t* U, uint32_t* D, Grid
             for (int i = 0; i < kJPer; ++i) {
                 if (!(pu[i] & kMark)) {
                     pu[i] = U[pu[i]];
-                    U[vid[i]] = pu[i];
+                    if (hops) U[vid[i]] = pu[i];
                     pending = true;
                 }
                 if (!(pd[i] & kMark)) {
                     pd[i] = D[pd[i]];
-                    D[vid[i]] = pd[i];
+                    if (hops) D[vid[i]] = pd[i];
                     pending = true;
                 }
             }
@@ -410,23 +548,35 @@ __global__ __launch_bounds__(kBlock) void k_chase(uint32_t* U, uint32_t* D, Grid
         slot[i] = h;
     }
     __syncthreads();
-    // number the occupied slots in slot order; list their keys
-    constexpr int kSlotsPer = kHash / kBlock;
-    uint32_t occ = 0;
+    // number the occupied slots: wave w scans slots [w*kHash/4, (w+1)*kHash/4)
+    // row by row (64 consecutive slots per row), so LDS reads are conflict-free
+    constexpr int kRows = kHash / kBlock;
+    const int lane = lane_id(), w = wave_id();
+    const uint64_t lt = lanemask_lt();
+    uint32_t wcount = 0;
 #pragma unroll
-    for (int i = 0; i < kSlotsPer; ++i) occ += table[t * kSlotsPer + i] != kEmpty;
-    uint32_t total;
-    uint32_t j = block_exclusive_scan(occ, tmp, &total);
+    for (int i = 0; i < kRows; ++i)
+        wcount += uint32_t(__popcll(__ballot(table[w * (kHash / kWavesPerBlock) + i * kWave + lane] != kEmpty)));
+    if (lane == 0) tmp[w] = wcount;
+    __syncthreads();
+    uint32_t j = 0, total = 0;
+#pragma unroll
+    for (int i = 0; i < kWavesPerBlock; ++i) {
+        j += (i < w) ? tmp[i] : 0u;
+        total += tmp[i];
+    }
     const size_t region = size_t(b) * kJV;
 #pragma unroll
-    for (int i = 0; i < kSlotsPer; ++i) {
-        const int sl = t * kSlotsPer + i;
+    for (int i = 0; i < kRows; ++i) {
+        const int sl = w * (kHash / kWavesPerBlock) + i * kWave + lane;
         const uint64_t k = table[sl];
+        const uint64_t occ = __ballot(k != kEmpty);
         if (k != kEmpty) {
-            dense[sl] = uint16_t(j);
-            rec[region + j] = k;
-            ++j;
+            const uint32_t jj = j + uint32_t(__popcll(occ & lt));
+            dense[sl] = uint16_t(jj);
+            rec[region + jj] = k;
         }
+        j += uint32_t(__popcll(occ));
     }
     if (t == 0) reg_cnt[b] = total;
     __syncthreads();
