@@ -150,6 +150,40 @@ int plmss_segment_batch(int32_t n_jobs, const plmss_job* jobs, void* workspace,
                         size_t workspace_bytes, void* stream);
 
 /*
+ * What a batch needs from a plan: needs[0] = total vertices, needs[1] = fields,
+ * needs[2] = neighbour-scan tiles, needs[3] = chase tiles (host array of 4).
+ * Returns a status.
+ */
+int32_t plmss_batch_needs(int32_t n_jobs, const plmss_job* jobs, int64_t* needs);
+
+/*
+ * Capacity plans: the batched segmentation with every launch sized for a
+ * capacity and every total read on the device, so that one hipGraph captures
+ * it once and replays it for any batch within the capacity (continuous
+ * batching, serving).  Same results as plmss_segment per job.
+ *   plmss_plan_create   capacity (all > 0) and element type; NULL on failure.
+ *   plmss_plan_workspace_bytes  device workspace the plan's calls need.
+ *   plmss_plan_set      writes the batch's descriptor tables and totals into
+ *                       the workspace (asynchronous copies on `stream`; waits
+ *                       for earlier work on `stream` first, since it reuses
+ *                       host staging buffers).  PLMSS_E_TOO_LARGE beyond the
+ *                       capacity.  jobs[i].order must be NULL.
+ *   plmss_plan_launch   enqueues the kernels on `stream` (capturable).
+ *   plmss_plan_launch_graph  the same through a hipGraph, captured on the
+ *                       first call (and again when the workspace changes).
+ * A plan is a host object; its calls must not run concurrently.
+ */
+typedef struct plmss_plan plmss_plan;
+plmss_plan* plmss_plan_create(int64_t max_vertices, int32_t max_fields, int64_t max_scan_tiles,
+                              int64_t max_chase_tiles, int32_t dtype);
+void plmss_plan_destroy(plmss_plan* plan);
+size_t plmss_plan_workspace_bytes(const plmss_plan* plan);
+int plmss_plan_set(plmss_plan* plan, int32_t n_jobs, const plmss_job* jobs, void* workspace,
+                   size_t workspace_bytes, void* stream);
+int plmss_plan_launch(plmss_plan* plan, void* workspace, size_t workspace_bytes, void* stream);
+int plmss_plan_launch_graph(plmss_plan* plan, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
  * Launch tracing, for measurement.  While a trace is active on the calling
  * host thread (between plmss_trace_begin and plmss_trace_end), every kernel
  * launch made by the calls above is bracketed by two hipEvents recorded on the

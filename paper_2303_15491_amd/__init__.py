@@ -14,7 +14,7 @@ import ctypes
 import os
 
 __all__ = ["PlmssError", "library", "segment", "order_field", "steepest", "compress", "ms_ids",
-           "segment_batch", "workspace_bytes", "batch_workspace_bytes"]
+           "segment_batch", "workspace_bytes", "batch_workspace_bytes", "batch_needs", "Plan"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libplmss.so")
@@ -59,6 +59,15 @@ _SIGNATURES = {
     "plmss_batch_workspace_bytes": ([ctypes.c_int32, ctypes.POINTER(Job)], ctypes.c_size_t),
     "plmss_segment_batch": ([ctypes.c_int32, ctypes.POINTER(Job), ctypes.c_void_p, ctypes.c_size_t,
                              ctypes.c_void_p], ctypes.c_int),
+    "plmss_batch_needs": ([ctypes.c_int32, ctypes.POINTER(Job), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int32),
+    "plmss_plan_create": ([ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32],
+                          ctypes.c_void_p),
+    "plmss_plan_destroy": ([ctypes.c_void_p], None),
+    "plmss_plan_workspace_bytes": ([ctypes.c_void_p], ctypes.c_size_t),
+    "plmss_plan_set": ([ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Job), ctypes.c_void_p, ctypes.c_size_t,
+                        ctypes.c_void_p], ctypes.c_int),
+    "plmss_plan_launch": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
+    "plmss_plan_launch_graph": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
     "plmss_trace_create": ([ctypes.c_int32], ctypes.c_void_p),
     "plmss_trace_destroy": ([ctypes.c_void_p], None),
     "plmss_trace_begin": ([ctypes.c_void_p], ctypes.c_int),
@@ -255,28 +264,40 @@ def _jobs(fields, outs):
     return arr
 
 
-def batch_workspace_bytes(fields) -> int:
+def _outs_for(fields):
     torch = _torch()
-    dummy = [{k: torch.empty(0, dtype=torch.int32) for k in ("asc", "desc", "ms", "info")} for _ in fields]
+    outs = []
+    for f in fields:
+        o = {k: torch.empty(f.shape, dtype=torch.int32, device=f.device) for k in ("asc", "desc", "ms")}
+        o["info"] = torch.empty(4, dtype=torch.int32, device=f.device)
+        outs.append(o)
+    return outs
+
+
+def batch_needs(fields):
+    """(vertices, fields, scan tiles, chase tiles) a batch needs from a Plan."""
     arr = (Job * len(fields))()
     for i, f in enumerate(fields):
         arr[i] = Job(1, dims_of(f.shape), _dtype_code(f), 1, 1, 1, None, None)
-    del dummy
+    needs = (ctypes.c_int64 * 4)()
+    _check(library().plmss_batch_needs(len(fields), arr, needs), "plmss_batch_needs")
+    return tuple(int(v) for v in needs)
+
+
+def batch_workspace_bytes(fields) -> int:
+    arr = (Job * len(fields))()
+    for i, f in enumerate(fields):
+        arr[i] = Job(1, dims_of(f.shape), _dtype_code(f), 1, 1, 1, None, None)
     return int(library().plmss_batch_workspace_bytes(len(fields), arr))
 
 
 def segment_batch(fields, workspace=None, stream=None, outs=None):
     """Segment many device fields of any sizes in one pass; returns one dict
     per field as :func:`segment` does (without ``order``)."""
-    torch = _torch()
     for f in fields:
         _field_check(f)
     if outs is None:
-        outs = []
-        for f in fields:
-            o = {k: torch.empty(f.shape, dtype=torch.int32, device=f.device) for k in ("asc", "desc", "ms")}
-            o["info"] = torch.empty(4, dtype=torch.int32, device=f.device)
-            outs.append(o)
+        outs = _outs_for(fields)
     arr = _jobs(fields, outs)
     lib = library()
     nbytes = lib.plmss_batch_workspace_bytes(len(fields), arr)
@@ -285,3 +306,48 @@ def segment_batch(fields, workspace=None, stream=None, outs=None):
     ws = _workspace(nbytes, fields[0].device, workspace)
     _check(lib.plmss_segment_batch(len(fields), arr, _ptr(ws), ws.numel(), _stream(stream)), "plmss_segment_batch")
     return outs
+
+
+class Plan:
+    """A capacity plan: batches of up to the given totals, launched through one
+    replayable hipGraph (see ``plmss_plan_*`` in plmss.h)."""
+
+    def __init__(self, max_vertices: int, max_fields: int, max_scan_tiles: int, max_chase_tiles: int,
+                 dtype=None, device="cuda"):
+        torch = _torch()
+        code = F64 if dtype == torch.float64 else F32
+        self._lib = library()
+        self._h = self._lib.plmss_plan_create(int(max_vertices), int(max_fields), int(max_scan_tiles),
+                                              int(max_chase_tiles), code)
+        if not self._h:
+            raise PlmssError(E_ARG, "plmss_plan_create")
+        nbytes = self._lib.plmss_plan_workspace_bytes(self._h)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self._jobs = None
+
+    def set(self, fields, outs=None, stream=None):
+        """Points the plan at a batch; returns the output dicts."""
+        for f in fields:
+            _field_check(f)
+        if outs is None:
+            outs = _outs_for(fields)
+        self._jobs = _jobs(fields, outs)  # kept alive with the tables
+        self._fields, self._outs = fields, outs
+        _check(self._lib.plmss_plan_set(self._h, len(fields), self._jobs, _ptr(self.workspace),
+                                        self.workspace.numel(), _stream(stream)), "plmss_plan_set")
+        return outs
+
+    def launch(self, graph: bool = True, stream=None):
+        fn = self._lib.plmss_plan_launch_graph if graph else self._lib.plmss_plan_launch
+        _check(fn(self._h, _ptr(self.workspace), self.workspace.numel(), _stream(stream)), "plmss_plan_launch")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.plmss_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

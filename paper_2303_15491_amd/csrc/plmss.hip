@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "common.h"
 #include "segment.h"
@@ -16,7 +17,8 @@ using namespace plmss;
 
 namespace {
 
-constexpr int64_t kMaxN = 2147483647;  // int32 labels
+constexpr int64_t kMaxN = 2147483647;      // int32 labels
+constexpr unsigned kPersistBlocks = 2048;  // grid of capacity-sized (replayable) launches
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -43,63 +45,70 @@ int check_dims(const plmss_dims& d, uint64_t* n_out) {
     return PLMSS_OK;
 }
 
-// Workspace of one field of n vertices (also the shape of a batch's
-// workspace, with n = the batch's total).
+// ---- shape classes ------------------------------------------------------------------
+// 3-D fields (nz > 1) use 64x8x16 scan tiles and 32x8x8 chase tiles; planar
+// fields (nz == 1) 64x16 and 64x32; lines (ny == nz == 1) 64x16 and 2048x1.
+constexpr int kClasses = 3;
+int class_of(const plmss_dims& d) { return d.nz > 1 ? 0 : (d.ny > 1 ? 1 : 2); }
+
+uint32_t s_tiles_of(const plmss_dims& d) {
+    return class_of(d) == 0 ? steepest_tiles(d.nx, d.ny, d.nz, 8, 16) : steepest_tiles(d.nx, d.ny, d.nz, 16, 1);
+}
+
+uint32_t j_tiles_of(const plmss_dims& d) {
+    switch (class_of(d)) {
+        case 0: return chase_tiles<JTile3>(d.nx, d.ny, d.nz);
+        case 1: return chase_tiles<JTile2>(d.nx, d.ny, d.nz);
+        default: return chase_tiles<JTile1>(d.nx, d.ny, d.nz);
+    }
+}
+
+// ---- workspace ----------------------------------------------------------------------
+
 struct Work {
-    uint8_t* keys[2];        // u64[npad] each: sort keys (ping-pong).  keys[0] also holds
-                             // the tile-compressed pointers U, D (u32[npad] each) and
-                             // keys[1] the per-block pair lists
-    uint32_t* vals[2];       // u32[npad] each: sort values
-    uint32_t* rank_of;       // u32[npad]: MS id of each listed pair (dense index)
-    uint32_t* reg_cnt;       // u32[nregions]: pairs listed per chase tile
-    uint32_t* reg_off;       // u32[nregions]: their exclusive prefix
-    uint32_t* hist;          // u32[kRadix * max(kWorkers, ntiles)]
-    uint32_t* dtotal;        // u32[kRadix]
-    uint32_t* partial;       // u32[kWorkers]
-    uint32_t* counters;      // u32[64]: [0] = #pairs listed, [1] = K
-    uint8_t* extra;          // batch tables
+    uint8_t* keys[2];    // u64[max(npad, regions*kJV)] each: sort keys (ping-pong).
+                         // keys[0] also holds the tile-compressed pointers U, D
+                         // (u32[npad] each) and keys[1] the per-tile pair lists
+    uint32_t* vals[2];   // u32[npad] each: sort values
+    uint32_t* rank_of;   // u32[npad]: MS id of each listed pair (dense index)
+    uint32_t* reg_cnt;   // u32[regions]: pairs listed per chase tile
+    uint32_t* reg_off;   // u32[regions]: their exclusive prefix
+    uint32_t* hist;      // u32[kRadix * max(kWorkers, ntiles)]
+    uint32_t* dtotal;    // u32[kRadix]
+    uint32_t* partial;   // u32[kWorkers]
+    uint32_t* counters;  // u32[64]: [0] = #pairs listed, [1] = K, [32..63] batch totals
+    uint32_t* fbase;     // u32[nfields]: first MS id of each field
+    FieldDesc* tables;   // batch tables: all fields, then one slot range per class
     uint64_t npad;
 };
 
 struct Sizes {
-    size_t keys, vals, rank, regions, hist, dtotal, partial, counters, extra, total;
+    size_t keys, vals, rank, regions, hist, dtotal, partial, counters, fbase, tables, total;
     uint64_t npad;
 };
 
 uint64_t n_tiles(uint64_t n) { return (n + kTile - 1) / kTile; }
 
-// Tile grid of the chase kernel for a field of dims d: 3-D, 2-D or 1-D tiles.
-struct ChasePlan {
-    int kind;            // 3, 2 or 1
-    uint64_t regions;    // number of tiles
-};
-
-ChasePlan chase_plan(const plmss_dims& d) {
-    const GridDims g{int32_t(d.nx), int32_t(d.ny), int32_t(d.nz)};
-    if (d.nz > 1) return {3, chase_blocks<JTile3>(g)};
-    if (d.ny > 1) return {2, chase_blocks<JTile2>(g)};
-    return {1, chase_blocks<JTile1>(g)};
-}
-
-Sizes work_sizes(uint64_t n, uint64_t regions, size_t extra) {
+// nv vertices, `regions` chase tiles; table_stride > 0 reserves batch tables
+// of that many entries per range (all fields + 3 classes).
+Sizes work_sizes(uint64_t nv, uint64_t regions, uint64_t nfields, uint64_t table_stride) {
     Sizes s;
-    s.npad = align_up(n, kBlock);
+    s.npad = align_up(std::max<uint64_t>(nv, 1), kBlock);
     const uint64_t rec = std::max<uint64_t>(s.npad, regions * kJV);
     s.keys = align_up(8 * rec, 256);
     s.vals = align_up(4 * s.npad, 256);
     s.rank = align_up(4 * s.npad, 256);
     s.regions = align_up(4 * std::max<uint64_t>(regions, 1), 256);
-    s.hist = align_up(size_t(4) * kRadix * std::max<uint64_t>(kWorkers, n_tiles(n)), 256);
+    s.hist = align_up(size_t(4) * kRadix * std::max<uint64_t>(kWorkers, n_tiles(nv)), 256);
     s.dtotal = align_up(4 * kRadix, 256);
     s.partial = align_up(4 * kWorkers, 256);
     s.counters = 256;
-    s.extra = align_up(extra, 256);
+    s.fbase = align_up(4 * std::max<uint64_t>(nfields, 1), 256);
+    s.tables = table_stride ? align_up(sizeof(FieldDesc) * 4 * table_stride, 256) : 0;
     s.total = 2 * s.keys + 2 * s.vals + s.rank + 2 * s.regions + s.hist + s.dtotal + s.partial +
-              s.counters + s.extra;
+              s.counters + s.fbase + s.tables;
     return s;
 }
-
-Sizes work_sizes(const plmss_dims& d, uint64_t n) { return work_sizes(n, chase_plan(d).regions, 0); }
 
 Work carve(void* ws, const Sizes& s) {
     Work w;
@@ -120,9 +129,14 @@ Work carve(void* ws, const Sizes& s) {
     w.dtotal = reinterpret_cast<uint32_t*>(take(s.dtotal));
     w.partial = reinterpret_cast<uint32_t*>(take(s.partial));
     w.counters = reinterpret_cast<uint32_t*>(take(s.counters));
-    w.extra = take(s.extra);
+    w.fbase = reinterpret_cast<uint32_t*>(take(s.fbase));
+    w.tables = s.tables ? reinterpret_cast<FieldDesc*>(take(s.tables)) : nullptr;
     w.npad = s.npad;
     return w;
+}
+
+bool ws_ok(const void* ws, size_t have, size_t need) {
+    return ws != nullptr && have >= need && (reinterpret_cast<uintptr_t>(ws) % 256) == 0;
 }
 
 int launch_status() { return hipGetLastError() == hipSuccess ? PLMSS_OK : PLMSS_E_HIP; }
@@ -134,7 +148,7 @@ unsigned grid_for(uint64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
 // bracketed by two hipEvents recorded on the launch stream.
 
 struct Trace {
-    hipEvent_t* ev = nullptr;   // 2 per launch
+    hipEvent_t* ev = nullptr;  // 2 per launch
     int32_t* kind = nullptr;
     int32_t cap = 0;
     int32_t n = 0;
@@ -196,9 +210,16 @@ void sort_order(const T* f, uint32_t n, int32_t* order, const Work& w, int32_t* 
                kRadixBits * (passes - 1), false, w, info, s);
 }
 
+void order_any(const void* field, int32_t dtype, uint32_t n, int32_t* order, const Work& w,
+               int32_t* info, hipStream_t s) {
+    if (dtype == PLMSS_F32)
+        sort_order<float, uint32_t>(static_cast<const float*>(field), n, order, w, info, s);
+    else
+        sort_order<double, uint64_t>(static_cast<const double*>(field), n, order, w, info, s);
+}
+
 // Sorts the listed (asc, desc) pair keys in keys[0]/vals[0] (count in
-// counters[0], known only on the device); returns the buffer index holding the
-// result.
+// counters[0], known only on the device); returns the buffer holding the result.
 int sort_pairs(int bits, const Work& w, hipStream_t s) {
     const int passes = (bits + kRadixBits - 1) / kRadixBits;
     uint64_t* keys[2] = {reinterpret_cast<uint64_t*>(w.keys[0]),
@@ -213,95 +234,302 @@ int sort_pairs(int bits, const Work& w, hipStream_t s) {
     return cur;
 }
 
-// Exclusive prefix of in[0..m) into out (host-known m).
-void prefix_sum(const uint32_t* in, uint32_t m, uint32_t* out, uint32_t* total, const Work& w,
-                hipStream_t s) {
-    launch(PLMSS_KERNEL_PREFIX, s, [&] { k_sum_reduce<<<kWorkers, kBlock, 0, s>>>(in, nullptr, m, w.partial); });
+// Exclusive prefix of in[0..m) into out; m from m_dev when given.
+void prefix_sum(const uint32_t* in, const uint32_t* m_dev, uint32_t m, uint32_t* out,
+                uint32_t* total, const Work& w, hipStream_t s) {
+    launch(PLMSS_KERNEL_PREFIX, s, [&] { k_sum_reduce<<<kWorkers, kBlock, 0, s>>>(in, m_dev, m, w.partial); });
     launch(PLMSS_KERNEL_PREFIX, s, [&] { k_scan_partials<<<1, kBlock, 0, s>>>(w.partial, kWorkers, total); });
-    launch(PLMSS_KERNEL_PREFIX, s, [&] { k_scan_apply<<<kWorkers, kBlock, 0, s>>>(in, nullptr, m, w.partial, out); });
+    launch(PLMSS_KERNEL_PREFIX, s, [&] { k_scan_apply<<<kWorkers, kBlock, 0, s>>>(in, m_dev, m, w.partial, out); });
 }
 
-// MS ids from the pairs listed per chase tile (rec = keys[1], counts in
-// reg_cnt, slots in ms): compact, sort, rank, relabel.
-void ms_from_pairs(int32_t* ms, uint32_t n, uint32_t nregions, int bn, int32_t* info, const Work& w,
-                   hipStream_t s) {
-    uint64_t* rec = reinterpret_cast<uint64_t*>(w.keys[1]);
-    prefix_sum(w.reg_cnt, nregions, w.reg_off, w.counters + 0, w, s);
-    launch(PLMSS_KERNEL_COMPACT, s, [&] {
-        k_compact_pairs<<<nregions, kBlock, 0, s>>>(w.reg_cnt, w.reg_off, rec,
-                                                     reinterpret_cast<uint64_t*>(w.keys[0]), w.vals[0]);
+// ---- one launch over a set of fields -------------------------------------------------------
+
+// The fields of one call, grouped by shape class.  `all` lists every field in
+// launch order (vertex numbering); cls[c] the fields of class c.
+struct LaunchSet {
+    Fields all;
+    Fields cls[kClasses];
+    bool used[kClasses];
+    unsigned grid_s[kClasses], grid_j[kClasses];
+    uint32_t regions;             // host total of chase tiles (all classes)
+    const uint32_t* regions_dev;  // or on the device
+    bool capacity;                // grids sized for a capacity, totals on the device
+    int bn;
+    int32_t dtype;
+};
+
+template <bool RESOLVE, class Src>
+void launch_steepest_cls(int c, const Fields& F, unsigned grid, uint32_t* up, uint32_t* dn, hipStream_t s) {
+    if (grid == 0) return;
+    launch(PLMSS_KERNEL_STEEPEST, s, [&] {
+        if (c == 0)
+            k_steepest<Src, 8, 16, RESOLVE><<<grid, kBlock, 0, s>>>(F, up, dn);
+        else
+            k_steepest<Src, 16, 1, RESOLVE><<<grid, kBlock, 0, s>>>(F, up, dn);
     });
-    const int r = sort_pairs(2 * bn, w, s);
+}
+
+template <bool RESOLVE>
+void launch_steepest_any(int c, const Fields& F, unsigned grid, int32_t dtype, bool order, uint32_t* up,
+                         uint32_t* dn, hipStream_t s) {
+    if (order)
+        launch_steepest_cls<RESOLVE, RankOrder>(c, F, grid, up, dn, s);
+    else if (dtype == PLMSS_F32)
+        launch_steepest_cls<RESOLVE, FieldOrder<float, uint32_t>>(c, F, grid, up, dn, s);
+    else
+        launch_steepest_cls<RESOLVE, FieldOrder<double, uint64_t>>(c, F, grid, up, dn, s);
+}
+
+template <bool CHASE>
+void launch_chase_cls(int c, const Fields& F, unsigned grid, uint32_t* U, uint32_t* D, int bn, const Work& w,
+                      hipStream_t s) {
+    if (grid == 0) return;
+    uint64_t* rec = reinterpret_cast<uint64_t*>(w.keys[1]);
+    launch(PLMSS_KERNEL_JUMP, s, [&] {
+        if (c == 0)
+            k_chase<JTile3, CHASE><<<grid, kBlock, 0, s>>>(F, U, D, bn, rec, w.reg_cnt);
+        else if (c == 1)
+            k_chase<JTile2, CHASE><<<grid, kBlock, 0, s>>>(F, U, D, bn, rec, w.reg_cnt);
+        else
+            k_chase<JTile1, CHASE><<<grid, kBlock, 0, s>>>(F, U, D, bn, rec, w.reg_cnt);
+    });
+}
+
+void launch_ms_final_cls(int c, const Fields& F, unsigned grid, const Work& w, hipStream_t s) {
+    if (grid == 0) return;
+    launch(PLMSS_KERNEL_MS_FINAL, s, [&] {
+        if (c == 0)
+            k_ms_final<JTile3><<<grid, kBlock, 0, s>>>(F, w.reg_off, w.rank_of, w.fbase);
+        else if (c == 1)
+            k_ms_final<JTile2><<<grid, kBlock, 0, s>>>(F, w.reg_off, w.rank_of, w.fbase);
+        else
+            k_ms_final<JTile1><<<grid, kBlock, 0, s>>>(F, w.reg_off, w.rank_of, w.fbase);
+    });
+}
+
+// MS ids from the pairs listed per chase tile: compact, sort, rank, per-field
+// bases, relabel.
+void ms_from_pairs(const LaunchSet& L, const Work& w, hipStream_t s) {
+    uint64_t* rec = reinterpret_cast<uint64_t*>(w.keys[1]);
+    prefix_sum(w.reg_cnt, L.regions_dev, L.regions, w.reg_off, w.counters + 0, w, s);
+    const unsigned cgrid = L.capacity ? kPersistBlocks : std::max(1u, L.regions);
+    launch(PLMSS_KERNEL_COMPACT, s, [&] {
+        k_compact_pairs<<<cgrid, kBlock, 0, s>>>(w.reg_cnt, w.reg_off, L.regions_dev, L.regions, rec,
+                                                 reinterpret_cast<uint64_t*>(w.keys[0]), w.vals[0]);
+    });
+    const int r = sort_pairs(2 * L.bn, w, s);
     const uint64_t* sk = reinterpret_cast<const uint64_t*>(w.keys[r]);
     launch(PLMSS_KERNEL_RANK, s, [&] { k_rank_reduce<<<kWorkers, kBlock, 0, s>>>(sk, w.counters + 0, w.partial); });
     launch(PLMSS_KERNEL_PREFIX, s, [&] { k_scan_partials<<<1, kBlock, 0, s>>>(w.partial, kWorkers, w.counters + 1); });
     launch(PLMSS_KERNEL_RANK, s, [&] {
         k_rank_apply<<<kWorkers, kBlock, 0, s>>>(sk, w.vals[r], w.counters + 0, w.partial, w.rank_of);
     });
-    if (info) launch(PLMSS_KERNEL_MISC, s, [&] { k_store_k<<<1, 64, 0, s>>>(info, w.counters + 1); });
-    launch(PLMSS_KERNEL_MS_FINAL, s, [&] {
-        k_ms_final<<<unsigned((uint64_t(n) + 4 * kBlock - 1) / (4 * kBlock)), kBlock, 0, s>>>(
-            ms, n, w.reg_off, w.rank_of);
+    launch(PLMSS_KERNEL_RANK, s, [&] {
+        k_field_base<<<1, kBlock, 0, s>>>(L.all, sk, w.vals[r], w.counters + 0, w.counters + 1, w.rank_of,
+                                          L.bn, w.fbase);
     });
+    for (int c = 0; c < kClasses; ++c)
+        if (L.used[c]) launch_ms_final_cls(c, L.cls[c], L.grid_j[c], w, s);
 }
 
-// Labels and pair lists over chase tiles of the plan's shape.
-template <bool CHASE>
-void launch_chase(const ChasePlan& cp, const plmss_dims& d, uint32_t* U, uint32_t* D, int32_t* desc,
-                  int32_t* asc, int bn, int32_t* ms, int32_t* info, const Work& w, hipStream_t s) {
-    const GridDims g{int32_t(d.nx), int32_t(d.ny), int32_t(d.nz)};
-    uint64_t* rec = reinterpret_cast<uint64_t*>(w.keys[1]);
-    const unsigned blocks = unsigned(cp.regions);
-    launch(PLMSS_KERNEL_JUMP, s, [&] {
-        if (cp.kind == 3)
-            k_chase<JTile3, CHASE><<<blocks, kBlock, 0, s>>>(U, D, g, desc, asc, bn, rec, w.reg_cnt, ms, info);
-        else if (cp.kind == 2)
-            k_chase<JTile2, CHASE><<<blocks, kBlock, 0, s>>>(U, D, g, desc, asc, bn, rec, w.reg_cnt, ms, info);
-        else
-            k_chase<JTile1, CHASE><<<blocks, kBlock, 0, s>>>(U, D, g, desc, asc, bn, rec, w.reg_cnt, ms, info);
-    });
+// The segmentation of every field of L (an order field only for a single
+// field: `order` != nullptr).
+void run_set(const LaunchSet& L, const void* field, int32_t* order, uint32_t n_single, const Work& w,
+             hipStream_t s) {
+    uint32_t* U = reinterpret_cast<uint32_t*>(w.keys[0]);
+    uint32_t* D = U + w.npad;
+    launch(PLMSS_KERNEL_MISC, s, [&] { k_init<<<1, 64, 0, s>>>(nullptr, w.counters, 8); });
+    launch(PLMSS_KERNEL_MISC, s, [&] { k_init_fields<<<L.capacity ? 64u : 1u, kBlock, 0, s>>>(L.all); });
+    if (order) order_any(field, L.dtype, n_single, order, w, L.all.one.info, s);
+    for (int c = 0; c < kClasses; ++c)
+        if (L.used[c]) {
+            Fields F = L.cls[c];
+            if (order) F.one.src = order;
+            launch_steepest_any<true>(c, F, L.grid_s[c], L.dtype, order != nullptr, U, D, s);
+        }
+    for (int c = 0; c < kClasses; ++c)
+        if (L.used[c]) launch_chase_cls<true>(c, L.cls[c], L.grid_j[c], U, D, L.bn, w, s);
+    ms_from_pairs(L, w, s);
 }
 
-// Tile shape of the neighbour scan: kTX x TY columns over ZC planes (3-D), or
-// kTX x 16 rectangles (2-D and 1-D fields).
-template <bool RESOLVE, class Src>
-void launch_steepest(Src src, const plmss_dims& d, uint32_t* up, uint32_t* dn, int32_t* info,
-                     hipStream_t s) {
-    const GridDims g{int32_t(d.nx), int32_t(d.ny), int32_t(d.nz)};
-    launch(PLMSS_KERNEL_STEEPEST, s, [&] {
-        if (d.nz > 1)
-            k_steepest<Src, 8, 16, RESOLVE><<<steepest_blocks(g, 8, 16), kBlock, 0, s>>>(src, g, up, dn, info);
-        else
-            k_steepest<Src, 16, 1, RESOLVE><<<steepest_blocks(g, 16, 1), kBlock, 0, s>>>(src, g, up, dn, info);
-    });
+FieldDesc desc_of(const plmss_job& j, uint32_t vbase, uint32_t sbase, uint32_t jbase, uint32_t index = 0) {
+    FieldDesc d;
+    d.index = index;
+    d.src = j.field;
+    d.asc = j.asc;
+    d.desc = j.desc;
+    d.ms = j.ms;
+    d.info = j.info;
+    d.nx = int32_t(j.dims.nx);
+    d.ny = int32_t(j.dims.ny);
+    d.nz = int32_t(j.dims.nz);
+    d.vbase = vbase;
+    d.sbase = sbase;
+    d.jbase = jbase;
+    return d;
 }
 
-template <bool RESOLVE>
-void steepest_any(const void* field, const int32_t* order, const plmss_dims& d, int32_t dtype,
-                  uint32_t* up, uint32_t* dn, int32_t* info, hipStream_t s) {
-    if (order)
-        launch_steepest<RESOLVE>(RankOrder{order}, d, up, dn, info, s);
-    else if (dtype == PLMSS_F32)
-        launch_steepest<RESOLVE>(FieldOrder<float, uint32_t>{static_cast<const float*>(field)}, d, up,
-                                 dn, info, s);
-    else
-        launch_steepest<RESOLVE>(FieldOrder<double, uint64_t>{static_cast<const double*>(field)}, d,
-                                 up, dn, info, s);
+Fields fields_one(const FieldDesc& d, uint32_t s_tiles, uint32_t j_tiles) {
+    Fields F{};
+    F.table = nullptr;
+    F.n = 1;
+    F.s_tiles = s_tiles;
+    F.j_tiles = j_tiles;
+    F.region0 = 0;
+    F.dev_tiles = nullptr;
+    F.one = d;
+    return F;
 }
 
-void order_any(const void* field, int32_t dtype, uint32_t n, int32_t* order, const Work& w,
-               int32_t* info, hipStream_t s) {
-    if (dtype == PLMSS_F32)
-        sort_order<float, uint32_t>(static_cast<const float*>(field), n, order, w, info, s);
-    else
-        sort_order<double, uint64_t>(static_cast<const double*>(field), n, order, w, info, s);
+// A single field: everything passed by value, one block per tile.
+LaunchSet single_set(const plmss_job& job, uint64_t n) {
+    LaunchSet L{};
+    const int c = class_of(job.dims);
+    const uint32_t st = s_tiles_of(job.dims), jt = j_tiles_of(job.dims);
+    const FieldDesc d = desc_of(job, 0, 0, 0);
+    L.all = fields_one(d, st, jt);
+    for (int k = 0; k < kClasses; ++k) L.used[k] = false;
+    L.used[c] = true;
+    L.cls[c] = fields_one(d, st, jt);
+    L.grid_s[c] = st;
+    L.grid_j[c] = jt;
+    L.regions = jt;
+    L.regions_dev = nullptr;
+    L.capacity = false;
+    L.bn = id_bits(n);
+    L.dtype = job.dtype;
+    return L;
 }
 
-bool ws_ok(const void* ws, size_t have, size_t need) {
-    return ws != nullptr && have >= need && (reinterpret_cast<uintptr_t>(ws) % 256) == 0;
+// Host-side layout of a batch: descriptors of all fields and of each class
+// (class-local tile bases), totals.
+struct BatchLayout {
+    std::vector<FieldDesc> all, cls[kClasses];
+    uint32_t s_tiles[kClasses] = {0, 0, 0}, j_tiles[kClasses] = {0, 0, 0}, region0[kClasses] = {0, 0, 0};
+    uint64_t nv = 0, regions = 0;
+};
+
+int batch_layout(int32_t n_jobs, const plmss_job* jobs, BatchLayout* B) {
+    if (n_jobs < 1 || !jobs) return PLMSS_E_ARG;
+    const int32_t dtype = jobs[0].dtype;
+    std::vector<uint64_t> nvert(n_jobs);
+    for (int32_t i = 0; i < n_jobs; ++i) {
+        const plmss_job& j = jobs[i];
+        if (!j.field || !j.asc || !j.desc || !j.ms || j.order) return PLMSS_E_ARG;
+        if (j.dtype != PLMSS_F32 && j.dtype != PLMSS_F64) return PLMSS_E_ARG;
+        if (j.dtype != dtype) return PLMSS_E_ARG;
+        int rc = check_dims(j.dims, &nvert[i]);
+        if (rc) return rc;
+        B->nv += nvert[i];
+        if (B->nv > uint64_t(kMaxN)) return PLMSS_E_TOO_LARGE;
+    }
+    uint32_t vb = 0;
+    for (int32_t i = 0; i < n_jobs; ++i) {
+        const int c = class_of(jobs[i].dims);
+        const FieldDesc d = desc_of(jobs[i], vb, B->s_tiles[c], B->j_tiles[c], uint32_t(i));
+        B->all.push_back(d);
+        B->cls[c].push_back(d);
+        vb += uint32_t(nvert[i]);
+        B->s_tiles[c] += s_tiles_of(jobs[i].dims);
+        B->j_tiles[c] += j_tiles_of(jobs[i].dims);
+    }
+    // pair-list regions: class 0 tiles first, then class 1, then class 2
+    B->region0[1] = B->j_tiles[0];
+    B->region0[2] = B->j_tiles[0] + B->j_tiles[1];
+    B->regions = uint64_t(B->j_tiles[0]) + B->j_tiles[1] + B->j_tiles[2];
+    if (B->regions * kJV > 0xffffffffull) return PLMSS_E_TOO_LARGE;
+    return PLMSS_OK;
+}
+
+// Table image: range 0 = all fields, range 1 + c = class c, `stride` entries each.
+std::vector<FieldDesc> table_image(const BatchLayout& B, size_t stride) {
+    std::vector<FieldDesc> img(4 * stride);
+    std::copy(B.all.begin(), B.all.end(), img.begin());
+    for (int c = 0; c < kClasses; ++c) std::copy(B.cls[c].begin(), B.cls[c].end(), img.begin() + (1 + c) * stride);
+    return img;
+}
+
+// A batch with host-known totals over the device tables.
+LaunchSet batch_set(const BatchLayout& B, const FieldDesc* tables, size_t stride, int32_t dtype, int bn) {
+    LaunchSet L{};
+    L.all = Fields{};
+    L.all.table = tables;
+    L.all.n = uint32_t(B.all.size());
+    for (int c = 0; c < kClasses; ++c) {
+        Fields F{};
+        F.table = tables + (1 + c) * stride;
+        F.n = uint32_t(B.cls[c].size());
+        F.s_tiles = B.s_tiles[c];
+        F.j_tiles = B.j_tiles[c];
+        F.region0 = B.region0[c];
+        F.dev_tiles = nullptr;
+        L.cls[c] = F;
+        L.used[c] = F.n > 0;
+        L.grid_s[c] = B.s_tiles[c];
+        L.grid_j[c] = B.j_tiles[c];
+    }
+    L.regions = uint32_t(B.regions);
+    L.regions_dev = nullptr;
+    L.capacity = false;
+    L.bn = bn;
+    L.dtype = dtype;
+    return L;
+}
+
+// Device totals block of a capacity launch (u32, in counters[32..63]):
+//   [4c .. 4c+3]  class c: scan tiles, chase tiles, fields, first region
+//   [12 .. 15]    all fields: 0, 0, fields, 0
+//   [16]          regions (all classes)
+constexpr int kTot = 32;
+
+LaunchSet capacity_set(const Work& w, size_t stride, unsigned grid_s, unsigned grid_j, uint32_t max_regions,
+                       int32_t dtype, int bn) {
+    const uint32_t* tot = w.counters + kTot;
+    LaunchSet L{};
+    L.all = Fields{};
+    L.all.table = w.tables;
+    L.all.n = uint32_t(stride);
+    L.all.dev_tiles = tot + 12;
+    for (int c = 0; c < kClasses; ++c) {
+        Fields F{};
+        F.table = w.tables + (1 + c) * stride;
+        F.n = uint32_t(stride);
+        F.dev_tiles = tot + 4 * c;
+        L.cls[c] = F;
+        L.used[c] = true;  // a class without fields runs empty grids
+        L.grid_s[c] = grid_s;
+        L.grid_j[c] = grid_j;
+    }
+    L.regions = max_regions;
+    L.regions_dev = tot + 16;
+    L.capacity = true;
+    L.bn = bn;
+    L.dtype = dtype;
+    return L;
 }
 
 }  // namespace
+
+// ---- capacity plans (batched launches that a hipGraph can replay) -----------------------
+
+struct plmss_plan {
+    int64_t max_vertices = 0;
+    int32_t max_fields = 0;
+    int64_t max_scan_tiles = 0;
+    int64_t max_chase_tiles = 0;
+    int32_t dtype = 0;
+    int bn = 1;
+    Sizes sizes{};
+    FieldDesc* pinned = nullptr;     // host staging of the tables
+    uint32_t* pinned_tot = nullptr;  // host staging of the totals
+    hipGraphExec_t exec = nullptr;
+    void* graph_ws = nullptr;            // workspace the graph was captured with
+    hipStream_t capture_stream = nullptr;  // private: capture never runs work
+};
+
+struct plmss_trace {
+    Trace t;
+};
 
 extern "C" {
 
@@ -310,7 +538,7 @@ const char* plmss_status_string(int code) {
         case PLMSS_OK: return "ok";
         case PLMSS_E_ARG: return "invalid argument (NULL pointer or bad enum value)";
         case PLMSS_E_DIMS: return "invalid grid dimensions (each must be >= 1)";
-        case PLMSS_E_TOO_LARGE: return "grid too large (more than 2^31-1 vertices)";
+        case PLMSS_E_TOO_LARGE: return "too large (more than 2^31-1 vertices, or beyond a plan's capacity)";
         case PLMSS_E_NAN: return "the field contains NaN";
         case PLMSS_E_WORKSPACE: return "workspace missing, misaligned or too small";
         case PLMSS_E_HIP: return "HIP runtime or launch error";
@@ -319,14 +547,14 @@ const char* plmss_status_string(int code) {
     }
 }
 
-const char* plmss_build_info(void) { return "libplmss 0.1 gfx950 wave64"; }
+const char* plmss_build_info(void) { return "libplmss 0.2 gfx950 wave64"; }
 
 size_t plmss_workspace_bytes(plmss_dims dims, int32_t dtype, int32_t with_order) {
     uint64_t n;
     if (check_dims(dims, &n) != PLMSS_OK) return 0;
     (void)dtype;
     (void)with_order;
-    return work_sizes(dims, n).total;
+    return work_sizes(n, j_tiles_of(dims), 1, 0).total;
 }
 
 int plmss_segment(const plmss_job* job, void* workspace, size_t workspace_bytes, void* stream) {
@@ -335,21 +563,13 @@ int plmss_segment(const plmss_job* job, void* workspace, size_t workspace_bytes,
     uint64_t n;
     int rc = check_dims(job->dims, &n);
     if (rc) return rc;
-    const ChasePlan cp = chase_plan(job->dims);
-    if (cp.regions * kJV > 0xffffffffull) return PLMSS_E_TOO_LARGE;
-    const Sizes sz = work_sizes(n, cp.regions, 0);
+    if (uint64_t(j_tiles_of(job->dims)) * kJV > 0xffffffffull) return PLMSS_E_TOO_LARGE;
+    const Sizes sz = work_sizes(n, j_tiles_of(job->dims), 1, 0);
     if (!ws_ok(workspace, workspace_bytes, sz.total)) return PLMSS_E_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const Work w = carve(workspace, sz);
-    const uint32_t n32 = uint32_t(n);
-    const int bn = id_bits(n);
-    uint32_t* U = reinterpret_cast<uint32_t*>(w.keys[0]);
-    uint32_t* D = U + w.npad;
-    launch(PLMSS_KERNEL_MISC, s, [&] { k_init<<<1, 64, 0, s>>>(job->info, w.counters, 64); });
-    if (job->order) order_any(job->field, job->dtype, n32, job->order, w, job->info, s);
-    steepest_any<true>(job->field, job->order, job->dims, job->dtype, U, D, job->info, s);
-    launch_chase<true>(cp, job->dims, U, D, job->desc, job->asc, bn, job->ms, job->info, w, s);
-    ms_from_pairs(job->ms, n32, uint32_t(cp.regions), bn, job->info, w, s);
+    const LaunchSet L = single_set(*job, n);
+    run_set(L, job->field, job->order, uint32_t(n), w, s);
     return launch_status();
 }
 
@@ -363,7 +583,7 @@ int plmss_order_field(const void* field, plmss_dims dims, int32_t dtype, int32_t
     uint64_t n;
     int rc = check_dims(dims, &n);
     if (rc) return rc;
-    const Sizes sz = work_sizes(dims, n);
+    const Sizes sz = work_sizes(n, j_tiles_of(dims), 1, 0);
     if (!ws_ok(workspace, workspace_bytes, sz.total)) return PLMSS_E_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const Work w = carve(workspace, sz);
@@ -381,8 +601,14 @@ int plmss_steepest(const void* field, const int32_t* order, plmss_dims dims, int
     if (rc) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (info) launch(PLMSS_KERNEL_MISC, s, [&] { k_init<<<1, 64, 0, s>>>(info, nullptr, 0); });
-    steepest_any<false>(field, order, dims, dtype, reinterpret_cast<uint32_t*>(up),
-                        reinterpret_cast<uint32_t*>(dn), info, s);
+    plmss_job j{};
+    j.field = order ? static_cast<const void*>(order) : field;
+    j.dims = dims;
+    j.info = info;
+    const Fields F = fields_one(desc_of(j, 0, 0, 0), s_tiles_of(dims), j_tiles_of(dims));
+    launch_steepest_any<false>(class_of(dims), F, s_tiles_of(dims), order ? PLMSS_F32 : dtype,
+                               order != nullptr, reinterpret_cast<uint32_t*>(up),
+                               reinterpret_cast<uint32_t*>(dn), s);
     return launch_status();
 }
 
@@ -397,7 +623,8 @@ int plmss_compress(int32_t* desc, int32_t* asc, int64_t n, void* stream) {
 
 size_t plmss_ms_workspace_bytes(int64_t n) {
     if (n < 1 || n > kMaxN) return 0;
-    return work_sizes(plmss_dims{n, 1, 1}, uint64_t(n)).total;
+    const plmss_dims d{n, 1, 1};
+    return work_sizes(uint64_t(n), j_tiles_of(d), 1, 0).total;
 }
 
 int plmss_ms_ids(const int32_t* asc, const int32_t* desc, int64_t n, int32_t* ms, int32_t* info,
@@ -406,40 +633,192 @@ int plmss_ms_ids(const int32_t* asc, const int32_t* desc, int64_t n, int32_t* ms
     if (n < 1) return PLMSS_E_DIMS;
     if (n > kMaxN) return PLMSS_E_TOO_LARGE;
     const plmss_dims d{n, 1, 1};
-    const ChasePlan cp = chase_plan(d);
-    const Sizes sz = work_sizes(uint64_t(n), cp.regions, 0);
+    const Sizes sz = work_sizes(uint64_t(n), j_tiles_of(d), 1, 0);
     if (!ws_ok(workspace, workspace_bytes, sz.total)) return PLMSS_E_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const Work w = carve(workspace, sz);
-    const uint32_t n32 = uint32_t(n);
-    const int bn = id_bits(uint64_t(n));
-    launch(PLMSS_KERNEL_MISC, s, [&] { k_init<<<1, 64, 0, s>>>(info, w.counters, 64); });
-    // the labels are only read
-    launch_chase<false>(cp, d, nullptr, nullptr, const_cast<int32_t*>(desc), const_cast<int32_t*>(asc), bn,
-                        ms, info, w, s);
-    ms_from_pairs(ms, n32, uint32_t(cp.regions), bn, info, w, s);
+    plmss_job j{};
+    j.field = asc;  // not read: only the labels are
+    j.dims = d;
+    j.asc = const_cast<int32_t*>(asc);
+    j.desc = const_cast<int32_t*>(desc);
+    j.ms = ms;
+    j.info = info;
+    const LaunchSet L = single_set(j, uint64_t(n));
+    launch(PLMSS_KERNEL_MISC, s, [&] { k_init<<<1, 64, 0, s>>>(info, w.counters, 8); });
+    launch_chase_cls<false>(class_of(d), L.cls[class_of(d)], L.grid_j[class_of(d)], nullptr, nullptr, L.bn, w, s);
+    ms_from_pairs(L, w, s);
     return launch_status();
 }
 
 size_t plmss_batch_workspace_bytes(int32_t n_jobs, const plmss_job* jobs) {
-    (void)n_jobs;
-    (void)jobs;
-    return 0;
+    BatchLayout B;
+    if (batch_layout(n_jobs, jobs, &B) != PLMSS_OK) return 0;
+    return work_sizes(B.nv, B.regions, uint64_t(n_jobs), uint64_t(n_jobs)).total;
 }
 
 int plmss_segment_batch(int32_t n_jobs, const plmss_job* jobs, void* workspace,
                         size_t workspace_bytes, void* stream) {
-    (void)n_jobs;
-    (void)jobs;
-    (void)workspace;
-    (void)workspace_bytes;
-    (void)stream;
-    return PLMSS_E_ARG;
+    BatchLayout B;
+    int rc = batch_layout(n_jobs, jobs, &B);
+    if (rc) return rc;
+    const Sizes sz = work_sizes(B.nv, B.regions, uint64_t(n_jobs), uint64_t(n_jobs));
+    if (!ws_ok(workspace, workspace_bytes, sz.total)) return PLMSS_E_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Work w = carve(workspace, sz);
+    const std::vector<FieldDesc> img = table_image(B, size_t(n_jobs));
+    if (hipMemcpyAsync(w.tables, img.data(), sizeof(FieldDesc) * img.size(), hipMemcpyHostToDevice, s) !=
+        hipSuccess)
+        return PLMSS_E_HIP;
+    const LaunchSet L = batch_set(B, w.tables, size_t(n_jobs), jobs[0].dtype, id_bits(B.nv));
+    run_set(L, nullptr, nullptr, 0, w, s);
+    // the host image must outlive the asynchronous copy
+    if (hipStreamSynchronize(s) != hipSuccess) return PLMSS_E_HIP;
+    return launch_status();
 }
 
-struct plmss_trace {
-    Trace t;
-};
+int32_t plmss_batch_needs(int32_t n_jobs, const plmss_job* jobs, int64_t* needs) {
+    if (!needs) return PLMSS_E_ARG;
+    BatchLayout B;
+    int rc = batch_layout(n_jobs, jobs, &B);
+    if (rc) return rc;
+    needs[0] = int64_t(B.nv);
+    needs[1] = n_jobs;
+    needs[2] = int64_t(B.s_tiles[0]) + B.s_tiles[1] + B.s_tiles[2];
+    needs[3] = int64_t(B.regions);
+    return PLMSS_OK;
+}
+
+plmss_plan* plmss_plan_create(int64_t max_vertices, int32_t max_fields, int64_t max_scan_tiles,
+                              int64_t max_chase_tiles, int32_t dtype) {
+    if (max_vertices < 1 || max_vertices > kMaxN || max_fields < 1 || max_scan_tiles < 1 ||
+        max_chase_tiles < 1 || (dtype != PLMSS_F32 && dtype != PLMSS_F64))
+        return nullptr;
+    if (uint64_t(max_chase_tiles) * kJV > 0xffffffffull) return nullptr;
+    plmss_plan* p = new (std::nothrow) plmss_plan;
+    if (!p) return nullptr;
+    p->max_vertices = max_vertices;
+    p->max_fields = max_fields;
+    p->max_scan_tiles = max_scan_tiles;
+    p->max_chase_tiles = max_chase_tiles;
+    p->dtype = dtype;
+    p->bn = id_bits(uint64_t(max_vertices));
+    p->sizes = work_sizes(uint64_t(max_vertices), uint64_t(max_chase_tiles), uint64_t(max_fields),
+                          uint64_t(max_fields));
+    if (hipHostMalloc(reinterpret_cast<void**>(&p->pinned), sizeof(FieldDesc) * 4 * size_t(max_fields)) !=
+        hipSuccess) {
+        delete p;
+        return nullptr;
+    }
+    if (hipHostMalloc(reinterpret_cast<void**>(&p->pinned_tot), 32 * sizeof(uint32_t)) != hipSuccess) {
+        (void)hipHostFree(p->pinned);
+        delete p;
+        return nullptr;
+    }
+    return p;
+}
+
+void plmss_plan_destroy(plmss_plan* p) {
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
+    if (p->pinned) (void)hipHostFree(p->pinned);
+    if (p->pinned_tot) (void)hipHostFree(p->pinned_tot);
+    delete p;
+}
+
+size_t plmss_plan_workspace_bytes(const plmss_plan* p) { return p ? p->sizes.total : 0; }
+
+int plmss_plan_set(plmss_plan* p, int32_t n_jobs, const plmss_job* jobs, void* workspace,
+                   size_t workspace_bytes, void* stream) {
+    if (!p) return PLMSS_E_ARG;
+    BatchLayout B;
+    int rc = batch_layout(n_jobs, jobs, &B);
+    if (rc) return rc;
+    if (jobs[0].dtype != p->dtype) return PLMSS_E_ARG;
+    if (n_jobs > p->max_fields || B.nv > uint64_t(p->max_vertices) ||
+        B.regions > uint64_t(p->max_chase_tiles) ||
+        uint64_t(B.s_tiles[0]) + B.s_tiles[1] + B.s_tiles[2] > uint64_t(p->max_scan_tiles))
+        return PLMSS_E_TOO_LARGE;
+    if (!ws_ok(workspace, workspace_bytes, p->sizes.total)) return PLMSS_E_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Work w = carve(workspace, p->sizes);
+    // a launch still in flight may read the staging buffers: let it finish
+    if (hipStreamSynchronize(s) != hipSuccess) return PLMSS_E_HIP;
+    const std::vector<FieldDesc> img = table_image(B, size_t(p->max_fields));
+    std::memcpy(p->pinned, img.data(), sizeof(FieldDesc) * img.size());
+    uint32_t* tot = p->pinned_tot;
+    std::memset(tot, 0, 32 * sizeof(uint32_t));
+    for (int c = 0; c < kClasses; ++c) {
+        tot[4 * c + 0] = B.s_tiles[c];
+        tot[4 * c + 1] = B.j_tiles[c];
+        tot[4 * c + 2] = uint32_t(B.cls[c].size());
+        tot[4 * c + 3] = B.region0[c];
+    }
+    tot[14] = uint32_t(n_jobs);
+    tot[16] = uint32_t(B.regions);
+    if (hipMemcpyAsync(w.tables, p->pinned, sizeof(FieldDesc) * img.size(), hipMemcpyHostToDevice, s) !=
+        hipSuccess)
+        return PLMSS_E_HIP;
+    if (hipMemcpyAsync(w.counters + kTot, tot, 32 * sizeof(uint32_t), hipMemcpyHostToDevice, s) != hipSuccess)
+        return PLMSS_E_HIP;
+    return PLMSS_OK;
+}
+
+int plmss_plan_launch(plmss_plan* p, void* workspace, size_t workspace_bytes, void* stream) {
+    if (!p) return PLMSS_E_ARG;
+    if (!ws_ok(workspace, workspace_bytes, p->sizes.total)) return PLMSS_E_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Work w = carve(workspace, p->sizes);
+    const unsigned gs = unsigned(std::min<int64_t>(kPersistBlocks, p->max_scan_tiles));
+    const unsigned gj = unsigned(std::min<int64_t>(kPersistBlocks, p->max_chase_tiles));
+    const LaunchSet L = capacity_set(w, size_t(p->max_fields), gs, gj, uint32_t(p->max_chase_tiles), p->dtype, p->bn);
+    run_set(L, nullptr, nullptr, 0, w, s);
+    return launch_status();
+}
+
+int plmss_plan_launch_graph(plmss_plan* p, void* workspace, size_t workspace_bytes, void* stream) {
+    if (!p) return PLMSS_E_ARG;
+    if (!ws_ok(workspace, workspace_bytes, p->sizes.total)) return PLMSS_E_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!p->exec || p->graph_ws != workspace) {
+        if (p->exec) {
+            (void)hipGraphExecDestroy(p->exec);
+            p->exec = nullptr;
+        }
+        // capture on a private stream (the caller's may be the null stream,
+        // which cannot be captured); the graph then runs on the caller's
+        if (!p->capture_stream &&
+            hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking) != hipSuccess) {
+            p->capture_stream = nullptr;
+            return PLMSS_E_HIP;
+        }
+        Trace* saved = g_trace;  // events are not recorded into a graph
+        g_trace = nullptr;
+        hipGraph_t graph = nullptr;
+        if (hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+            g_trace = saved;
+            return PLMSS_E_HIP;
+        }
+        const int rc = plmss_plan_launch(p, workspace, workspace_bytes, p->capture_stream);
+        const hipError_t e = hipStreamEndCapture(p->capture_stream, &graph);
+        g_trace = saved;
+        if (rc != PLMSS_OK || e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return PLMSS_E_HIP;
+        }
+        const hipError_t ie = hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ie != hipSuccess) {
+            p->exec = nullptr;
+            return PLMSS_E_HIP;
+        }
+        p->graph_ws = workspace;
+    }
+    return hipGraphLaunch(p->exec, s) == hipSuccess ? PLMSS_OK : PLMSS_E_HIP;
+}
+
+// ---- tracing ----------------------------------------------------------------------------
 
 plmss_trace* plmss_trace_create(int32_t max_launches) {
     if (max_launches < 1) return nullptr;

@@ -16,6 +16,7 @@ struct FieldOrder {
     using key_t = K;
     static constexpr bool kCheckNan = true;
     const T* f;
+    static __device__ __forceinline__ FieldOrder from(const void* p) { return {static_cast<const T*>(p)}; }
     __device__ __forceinline__ K load(size_t i, bool& nan) const {
         const T a = f[i];
         nan |= is_nan(a);
@@ -29,12 +30,78 @@ struct RankOrder {
     using key_t = uint32_t;
     static constexpr bool kCheckNan = false;
     const int32_t* order;
+    static __device__ __forceinline__ RankOrder from(const void* p) { return {static_cast<const int32_t*>(p)}; }
     __device__ __forceinline__ uint32_t load(size_t i, bool&) const { return uint32_t(order[i]) + 1u; }
 };
 
 struct GridDims {
     int32_t nx, ny, nz;
 };
+
+// One field of a launch.  Vertex v of the field is vertex vbase + v of the
+// launch's concatenated numbering (pointers U/D, MS pair keys); its labels are
+// written field-local.
+struct FieldDesc {
+    const void* src;   // values (FieldOrder) or order field (RankOrder)
+    int32_t* asc;
+    int32_t* desc;
+    int32_t* ms;
+    int32_t* info;     // {status, #minima, #maxima, K} or nullptr
+    int32_t nx, ny, nz;
+    uint32_t vbase;    // first launch-wide vertex id
+    uint32_t sbase;    // first steepest tile (within its shape class)
+    uint32_t jbase;    // first chase tile (within its shape class)
+    uint32_t index;    // position among all fields of the launch
+};
+
+// The fields of a launch: a device table (batches) or a single descriptor
+// passed by value.  Tile totals are host values, or device values for launches
+// sized for a capacity (graph replays over varying batches).
+struct Fields {
+    const FieldDesc* table;
+    uint32_t n;
+    uint32_t s_tiles, j_tiles;
+    uint32_t region0;           // chase tile t of this launch is pair-list region region0 + t
+    const uint32_t* dev_tiles;  // nullptr, or {s_tiles, j_tiles, n, region0} on the device
+    FieldDesc one;
+};
+
+__device__ __forceinline__ uint32_t fields_region0(const Fields& F) {
+    return F.dev_tiles ? F.dev_tiles[3] : F.region0;
+}
+
+__device__ __forceinline__ uint32_t fields_count(const Fields& F) {
+    return F.dev_tiles ? F.dev_tiles[2] : (F.table ? F.n : 1u);
+}
+
+// Field owning launch-wide tile `tile` (by sbase when STEEP, else jbase).
+template <bool STEEP>
+__device__ __forceinline__ FieldDesc field_of_tile(const Fields& F, uint32_t tile, uint32_t* index) {
+    if (!F.table) {
+        *index = 0;
+        return F.one;
+    }
+    uint32_t lo = 0, hi = fields_count(F);
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) / 2;
+        const uint32_t b = STEEP ? F.table[mid].sbase : F.table[mid].jbase;
+        if (b <= tile)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    *index = lo;
+    return F.table[lo];
+}
+
+// This block's tiles: a contiguous run, so that each XCD works on a compact
+// part of the grid.
+__device__ __forceinline__ void block_tiles(uint32_t total, uint32_t* first, uint32_t* last) {
+    const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
+    const uint32_t per = (total + gridDim.x - 1) / gridDim.x;
+    *first = min(total, b * per);
+    *last = min(total, *first + per);
+}
 
 // ---- neighbour codes --------------------------------------------------------------
 //
@@ -95,8 +162,8 @@ __device__ __forceinline__ void steepest_codes(const typename Src::key_t (*pl)[P
 
 constexpr uint32_t kMark = 0x80000000u;     // "this label is an extremum" in a resolved pointer
 constexpr uint32_t kMaxHops = 1u << 24;     // iteration cap of the pointer-chasing loops
-constexpr uint32_t kExit = 0x8000u;
-constexpr int kResolveRounds = 3;           // in-tile jumping sweeps      // local pointer: the target lies outside the tile
+constexpr uint32_t kExit = 0x8000u;         // local pointer: the target lies outside the tile
+constexpr int kResolveRounds = 3;           // in-tile jumping sweeps
 
 // Steepest neighbours of every vertex.
 //
@@ -132,8 +199,7 @@ struct SquarePlanes {
 };
 
 template <class Src, int TY, int ZC, bool RESOLVE>
-__global__ __launch_bounds__(kBlock) void k_steepest(Src src, GridDims g, uint32_t* up,
-                                                     uint32_t* dn, int32_t* info) {
+__global__ __launch_bounds__(kBlock) void k_steepest(Fields F, uint32_t* up, uint32_t* dn) {
     using K = typename Src::key_t;
     constexpr bool kSquares = sizeof(K) == 4;
     constexpr int PX = kTX + 2, PY = TY + 2, RPW = TY / kWavesPerBlock;
@@ -153,8 +219,17 @@ __global__ __launch_bounds__(kBlock) void k_steepest(Src src, GridDims g, uint32
     __shared__ uint32_t cnt_min, cnt_max;
     __shared__ int nan_seen;
     const int t = threadIdx.x, w = wave_id(), lane = lane_id();
+    uint32_t tfirst, tlast;
+    block_tiles(F.dev_tiles ? F.dev_tiles[0] : F.s_tiles, &tfirst, &tlast);
+    for (uint32_t tile = tfirst; tile < tlast; ++tile) {
+    uint32_t fidx;
+    const FieldDesc fd = field_of_tile<true>(F, tile, &fidx);
+    const Src src = Src::from(fd.src);
+    const GridDims g{fd.nx, fd.ny, fd.nz};
+    int32_t* const info = fd.info;
+    const uint32_t vbase = fd.vbase;
+    const uint32_t b = tile - fd.sbase;
     const int tx = (g.nx + kTX - 1) / kTX, ty = (g.ny + TY - 1) / TY;
-    const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
     const int bx = int(b % uint32_t(tx));
     const int by = int((b / uint32_t(tx)) % uint32_t(ty));
     const int bz = int(b / (uint32_t(tx) * uint32_t(ty)));
@@ -162,6 +237,7 @@ __global__ __launch_bounds__(kBlock) void k_steepest(Src src, GridDims g, uint32
     const int z1 = min(g.nz, z0 + ZC);
     const size_t sx = size_t(g.nx), sxy = size_t(g.nx) * size_t(g.ny);
     const int32_t S = int32_t(sxy);
+    __syncthreads();  // the previous tile's readers of LDS are done
     if (t == 0) {
         cnt_min = 0;
         cnt_max = 0;
@@ -300,7 +376,7 @@ __global__ __launch_bounds__(kBlock) void k_steepest(Src src, GridDims g, uint32
             }
             if (!RESOLVE) {
                 if (inside) {
-                    const size_t v = size_t(z) * sxy + size_t(y) * sx + size_t(x);
+                    const uint32_t v = vbase + uint32_t(z) * uint32_t(S) + uint32_t(y) * uint32_t(g.nx) + uint32_t(x);
                     up[v] = uint32_t(int32_t(v) + code_offset(cu, g.nx, S));
                     dn[v] = uint32_t(int32_t(v) + code_offset(cd, g.nx, S));
                 }
@@ -373,7 +449,8 @@ __global__ __launch_bounds__(kBlock) void k_steepest(Src src, GridDims g, uint32
         }
         // write-out: the end of the tile chain, resolved or to be followed.
         // Vertex ids fit in 32 bits.
-        const uint32_t tile0 = uint32_t(z0) * uint32_t(S) + uint32_t(y0) * uint32_t(g.nx) + uint32_t(x0);
+        const uint32_t tile0 =
+            vbase + uint32_t(z0) * uint32_t(S) + uint32_t(y0) * uint32_t(g.nx) + uint32_t(x0);
         auto gid = [&](uint32_t li) -> uint32_t {
             const uint32_t ax = li & (kTX - 1), ay = (li / kTX) & (TY - 1), az = li / (kTX * TY);
             return tile0 + az * uint32_t(S) + ay * uint32_t(g.nx) + ax;
@@ -411,11 +488,12 @@ __global__ __launch_bounds__(kBlock) void k_steepest(Src src, GridDims g, uint32
         if (cnt_max) atomicAdd(reinterpret_cast<uint32_t*>(info + 2), cnt_max);
         if (nan_seen) info[0] = -4;  // PLMSS_E_NAN
     }
+    (void)fidx;
+    }  // tiles
 }
 
-inline int steepest_blocks(const GridDims& g, int ty, int zc) {
-    const int tx = (g.nx + kTX - 1) / kTX, tyn = (g.ny + ty - 1) / ty, tz = (g.nz + zc - 1) / zc;
-    return tx * tyn * tz;
+inline uint32_t steepest_tiles(int64_t nx, int64_t ny, int64_t nz, int ty, int zc) {
+    return uint32_t(((nx + kTX - 1) / kTX) * ((ny + ty - 1) / ty) * ((nz + zc - 1) / zc));
 }
 
 // ---- chase, labels and MS pair listing ----------------------------------------------
@@ -444,8 +522,8 @@ using JTile2 = JTile<64, 32, 1>;
 using JTile1 = JTile<2048, 1, 1>;
 
 template <class T>
-inline unsigned chase_blocks(const GridDims& g) {
-    return unsigned(((g.nx + T::X - 1) / T::X) * ((g.ny + T::Y - 1) / T::Y) * ((g.nz + T::Z - 1) / T::Z));
+inline uint32_t chase_tiles(int64_t nx, int64_t ny, int64_t nz) {
+    return uint32_t(((nx + T::X - 1) / T::X) * ((ny + T::Y - 1) / T::Y) * ((nz + T::Z - 1) / T::Z));
 }
 
 __device__ __forceinline__ uint32_t pair_hash(uint64_t k) {
@@ -453,136 +531,146 @@ __device__ __forceinline__ uint32_t pair_hash(uint64_t k) {
     return (lo * 0x9E3779B1u) ^ (hi * 0x85EBCA77u) ^ (lo >> 15);
 }
 
+// Local coordinates of entry li of a chase tile.
+template <class T>
+__device__ __forceinline__ void jtile_xyz(const FieldDesc& fd, uint32_t lt, int li, int* x, int* y,
+                                          int* z) {
+    const int tx = (fd.nx + T::X - 1) / T::X, ty = (fd.ny + T::Y - 1) / T::Y;
+    const int x0 = int(lt % uint32_t(tx)) * T::X;
+    const int y0 = int((lt / uint32_t(tx)) % uint32_t(ty)) * T::Y;
+    const int z0 = int(lt / (uint32_t(tx) * uint32_t(ty))) * T::Z;
+    *x = x0 + li % T::X;
+    *y = y0 + (li / T::X) % T::Y;
+    *z = z0 + li / (T::X * T::Y);
+}
+
 // CHASE: labels from the tile-compressed pointers U/D (written back as they
-// are followed).  Otherwise the labels are read from desc/asc as given.
+// are followed).  Otherwise the labels are read from the field's desc/asc.
 template <class T, bool CHASE>
-__global__ __launch_bounds__(kBlock) void k_chase(uint32_t* U, uint32_t* D, GridDims g,
-                                                  int32_t* desc, int32_t* asc, int bn,
-                                                  uint64_t* rec, uint32_t* reg_cnt, int32_t* ms,
-                                                  int32_t* info) {
+__global__ __launch_bounds__(kBlock) void k_chase(Fields F, uint32_t* U, uint32_t* D, int bn,
+                                                  uint64_t* rec, uint32_t* reg_cnt) {
     __shared__ uint64_t table[kHash];
     __shared__ uint16_t dense[kHash];
     __shared__ uint32_t tmp[kWavesPerBlock];
-    const int t = threadIdx.x;
-    const int tx = (g.nx + T::X - 1) / T::X, ty = (g.ny + T::Y - 1) / T::Y;
-    const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
-    const int x0 = int(b % uint32_t(tx)) * T::X;
-    const int y0 = int((b / uint32_t(tx)) % uint32_t(ty)) * T::Y;
-    const int z0 = int(b / (uint32_t(tx) * uint32_t(ty))) * T::Z;
-    const size_t sx = size_t(g.nx), sxy = size_t(g.nx) * size_t(g.ny);
+    const int t = threadIdx.x, lane = lane_id(), w = wave_id();
+    uint32_t tfirst, tlast;
+    block_tiles(F.dev_tiles ? F.dev_tiles[1] : F.j_tiles, &tfirst, &tlast);
+    for (uint32_t tile = tfirst; tile < tlast; ++tile) {
+        uint32_t fidx;
+        const FieldDesc fd = field_of_tile<false>(F, tile, &fidx);
+        const uint32_t lt = tile - fd.jbase;
+        __syncthreads();  // the previous tile's readers of LDS are done
 #pragma unroll
-    for (int i = 0; i < kHash / kBlock; ++i) table[t + i * kBlock] = kEmpty;
-    uint32_t vid[kJPer], pu[kJPer], pd[kJPer];
-    bool ok[kJPer];
-#pragma unroll
-    for (int i = 0; i < kJPer; ++i) {
-        const int li = t + i * kBlock;
-        const int x = x0 + li % T::X, y = y0 + (li / T::X) % T::Y, z = z0 + li / (T::X * T::Y);
-        ok[i] = x < g.nx && y < g.ny && z < g.nz;
-        vid[i] = ok[i] ? uint32_t(size_t(z) * sxy + size_t(y) * sx + size_t(x)) : 0u;
-        if (CHASE) {
-            pu[i] = ok[i] ? U[vid[i]] : kMark;
-            pd[i] = ok[i] ? D[vid[i]] : kMark;
-        } else {
-            pu[i] = ok[i] ? uint32_t(desc[vid[i]]) : 0u;
-            pd[i] = ok[i] ? uint32_t(asc[vid[i]]) : 0u;
-        }
-    }
-    if (CHASE) {
-        // a pointer leads strictly up (down) its chain, so the hops end; the
-        // cap only guards against a malformed input
-        // the eight vertices of a thread advance together, so their gathers
-        // are in flight at the same time; from the second hop on, a pointer
-        // is written back so that later readers of the vertex jump further
-        bool pending = true;
-        uint32_t hops = 0;
-        while (pending && hops < kMaxHops) {
-            pending = false;
-#pragma unroll
-            for (int i = 0; i < kJPer; ++i) {
-                if (!(pu[i] & kMark)) {
-                    pu[i] = U[pu[i]];
-                    if (hops) U[vid[i]] = pu[i];
-                    pending = true;
-                }
-                if (!(pd[i] & kMark)) {
-                    pd[i] = D[pd[i]];
-                    if (hops) D[vid[i]] = pd[i];
-                    pending = true;
-                }
-            }
-            ++hops;
-        }
-        const bool capped = pending;
+        for (int i = 0; i < kHash / kBlock; ++i) table[t + i * kBlock] = kEmpty;
+        uint32_t lv[kJPer], pu[kJPer], pd[kJPer];
+        bool ok[kJPer];
 #pragma unroll
         for (int i = 0; i < kJPer; ++i) {
-            pu[i] &= ~kMark;
-            pd[i] &= ~kMark;
-            if (ok[i]) {
-                desc[vid[i]] = int32_t(pu[i]);
-                asc[vid[i]] = int32_t(pd[i]);
+            int x, y, z;
+            jtile_xyz<T>(fd, lt, t + i * kBlock, &x, &y, &z);
+            ok[i] = x < fd.nx && y < fd.ny && z < fd.nz;
+            lv[i] = ok[i] ? (uint32_t(z) * uint32_t(fd.ny) + uint32_t(y)) * uint32_t(fd.nx) + uint32_t(x) : 0u;
+            if (CHASE) {
+                pu[i] = ok[i] ? U[fd.vbase + lv[i]] : kMark;
+                pd[i] = ok[i] ? D[fd.vbase + lv[i]] : kMark;
+            } else {
+                pu[i] = ok[i] ? uint32_t(fd.desc[lv[i]]) + fd.vbase : 0u;
+                pd[i] = ok[i] ? uint32_t(fd.asc[lv[i]]) + fd.vbase : 0u;
             }
         }
-        if (capped && info) info[0] = -7;  // PLMSS_E_NOCONV
-    }
-    __syncthreads();
-    // insert every vertex's pair; slot[i] = its hash slot
-    uint32_t slot[kJPer];
+        if (CHASE) {
+            // the eight vertices of a thread advance together, so their
+            // gathers are in flight at the same time; from the second hop on,
+            // a pointer is written back so that later readers jump further
+            bool pending = true;
+            uint32_t hops = 0;
+            while (pending && hops < kMaxHops) {
+                pending = false;
 #pragma unroll
-    for (int i = 0; i < kJPer; ++i) {
-        slot[i] = 0;
-        if (!ok[i]) continue;
-        const uint64_t key = (uint64_t(pd[i]) << bn) | uint64_t(pu[i]);
-        uint32_t h = pair_hash(key) & (kHash - 1);
-        for (;;) {
-            uint64_t cur = table[h];
-            if (cur == kEmpty) {
-                cur = atomicCAS(reinterpret_cast<unsigned long long*>(&table[h]),
-                                static_cast<unsigned long long>(kEmpty),
-                                static_cast<unsigned long long>(key));
-                if (cur == kEmpty) cur = key;
+                for (int i = 0; i < kJPer; ++i) {
+                    if (!(pu[i] & kMark)) {
+                        pu[i] = U[pu[i]];
+                        if (hops) U[fd.vbase + lv[i]] = pu[i];
+                        pending = true;
+                    }
+                    if (!(pd[i] & kMark)) {
+                        pd[i] = D[pd[i]];
+                        if (hops) D[fd.vbase + lv[i]] = pd[i];
+                        pending = true;
+                    }
+                }
+                ++hops;
             }
-            if (cur == key) break;
-            h = (h + 1) & (kHash - 1);
+#pragma unroll
+            for (int i = 0; i < kJPer; ++i) {
+                pu[i] &= ~kMark;
+                pd[i] &= ~kMark;
+                if (ok[i]) {
+                    fd.desc[lv[i]] = int32_t(pu[i] - fd.vbase);
+                    fd.asc[lv[i]] = int32_t(pd[i] - fd.vbase);
+                }
+            }
+            if (pending && fd.info) fd.info[0] = -7;  // PLMSS_E_NOCONV
         }
-        slot[i] = h;
-    }
-    __syncthreads();
-    // number the occupied slots: wave w scans slots [w*kHash/4, (w+1)*kHash/4)
-    // row by row (64 consecutive slots per row), so LDS reads are conflict-free
-    constexpr int kRows = kHash / kBlock;
-    const int lane = lane_id(), w = wave_id();
-    const uint64_t lt = lanemask_lt();
-    uint32_t wcount = 0;
+        __syncthreads();
+        // insert every vertex's pair; slot[i] = its hash slot
+        uint32_t slot[kJPer];
 #pragma unroll
-    for (int i = 0; i < kRows; ++i)
-        wcount += uint32_t(__popcll(__ballot(table[w * (kHash / kWavesPerBlock) + i * kWave + lane] != kEmpty)));
-    if (lane == 0) tmp[w] = wcount;
-    __syncthreads();
-    uint32_t j = 0, total = 0;
-#pragma unroll
-    for (int i = 0; i < kWavesPerBlock; ++i) {
-        j += (i < w) ? tmp[i] : 0u;
-        total += tmp[i];
-    }
-    const size_t region = size_t(b) * kJV;
-#pragma unroll
-    for (int i = 0; i < kRows; ++i) {
-        const int sl = w * (kHash / kWavesPerBlock) + i * kWave + lane;
-        const uint64_t k = table[sl];
-        const uint64_t occ = __ballot(k != kEmpty);
-        if (k != kEmpty) {
-            const uint32_t jj = j + uint32_t(__popcll(occ & lt));
-            dense[sl] = uint16_t(jj);
-            rec[region + jj] = k;
+        for (int i = 0; i < kJPer; ++i) {
+            slot[i] = 0;
+            if (!ok[i]) continue;
+            const uint64_t key = (uint64_t(pd[i]) << bn) | uint64_t(pu[i]);
+            uint32_t h = pair_hash(key) & (kHash - 1);
+            for (;;) {
+                uint64_t cur = table[h];
+                if (cur == kEmpty) {
+                    cur = atomicCAS(reinterpret_cast<unsigned long long*>(&table[h]),
+                                    static_cast<unsigned long long>(kEmpty),
+                                    static_cast<unsigned long long>(key));
+                    if (cur == kEmpty) cur = key;
+                }
+                if (cur == key) break;
+                h = (h + 1) & (kHash - 1);
+            }
+            slot[i] = h;
         }
-        j += uint32_t(__popcll(occ));
-    }
-    if (t == 0) reg_cnt[b] = total;
-    __syncthreads();
+        __syncthreads();
+        // number the occupied slots: wave w scans slots [w*kHash/4, (w+1)*kHash/4)
+        // row by row (64 consecutive slots per row), so LDS reads are conflict-free
+        constexpr int kRows = kHash / kBlock;
+        const uint64_t lt_mask = lanemask_lt();
+        uint32_t wcount = 0;
 #pragma unroll
-    for (int i = 0; i < kJPer; ++i)
-        if (ok[i]) ms[vid[i]] = int32_t(uint32_t(region) + dense[slot[i]]);
+        for (int i = 0; i < kRows; ++i)
+            wcount += uint32_t(__popcll(__ballot(table[w * (kHash / kWavesPerBlock) + i * kWave + lane] != kEmpty)));
+        if (lane == 0) tmp[w] = wcount;
+        __syncthreads();
+        uint32_t j = 0, total = 0;
+#pragma unroll
+        for (int i = 0; i < kWavesPerBlock; ++i) {
+            j += (i < w) ? tmp[i] : 0u;
+            total += tmp[i];
+        }
+        const size_t region = size_t(fields_region0(F) + tile) * kJV;
+#pragma unroll
+        for (int i = 0; i < kRows; ++i) {
+            const int sl = w * (kHash / kWavesPerBlock) + i * kWave + lane;
+            const uint64_t k = table[sl];
+            const uint64_t occ = __ballot(k != kEmpty);
+            if (k != kEmpty) {
+                const uint32_t jj = j + uint32_t(__popcll(occ & lt_mask));
+                dense[sl] = uint16_t(jj);
+                rec[region + jj] = k;
+            }
+            j += uint32_t(__popcll(occ));
+        }
+        if (t == 0) reg_cnt[fields_region0(F) + tile] = total;
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kJPer; ++i)
+            if (ok[i]) fd.ms[lv[i]] = int32_t(uint32_t(region) + dense[slot[i]]);
+        (void)fidx;
+    }
 }
 
 // ---- path compression on global pointers (the step on its own) ---------------------
@@ -623,17 +711,21 @@ __global__ __launch_bounds__(kBlock) void k_jump(int32_t* desc, int32_t* asc, ui
 
 // ---- pair compaction and ranking ------------------------------------------------------
 
-// One block per tile region: copy its listed pairs to the dense arrays at
-// off[region] (exclusive prefix of reg_cnt): keys[o + j] = pair, vals[o + j] =
-// o + j (the dense index travels with the key through the sort).
+// One block per tile region (a persistent loop when the region count lives
+// on the device): copy its listed pairs to the dense arrays at off[region]
+// (exclusive prefix of reg_cnt): keys[o + j] = pair, vals[o + j] = o + j (the
+// dense index travels with the key through the sort).
 __global__ __launch_bounds__(kBlock) void k_compact_pairs(const uint32_t* reg_cnt,
-                                                          const uint32_t* off, const uint64_t* rec,
+                                                          const uint32_t* off, const uint32_t* count_ptr,
+                                                          uint32_t nregions, const uint64_t* rec,
                                                           uint64_t* keys, uint32_t* vals) {
-    const uint32_t r = blockIdx.x;
-    const uint32_t c = reg_cnt[r], o = off[r];
-    for (uint32_t j = threadIdx.x; j < c; j += kBlock) {
-        keys[o + j] = rec[size_t(r) * kJV + j];
-        vals[o + j] = o + j;
+    const uint32_t m = load_count(count_ptr, nregions);
+    for (uint32_t r = blockIdx.x; r < m; r += gridDim.x) {
+        const uint32_t c = reg_cnt[r], o = off[r];
+        for (uint32_t j = threadIdx.x; j < c; j += kBlock) {
+            keys[o + j] = rec[size_t(r) * kJV + j];
+            vals[o + j] = o + j;
+        }
     }
 }
 
@@ -689,22 +781,74 @@ __global__ __launch_bounds__(kBlock) void k_rank_apply(const uint64_t* keys, con
     }
 }
 
-// ms[v] = rank of its listed pair: rank_of[off[slot / kJV] + slot % kJV] with
-// slot = ms[v] on entry.  Four vertices per thread.
-__global__ __launch_bounds__(kBlock) void k_ms_final(int32_t* ms, uint32_t n, const uint32_t* off,
-                                                     const uint32_t* rank_of) {
-    const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
-    const uint32_t base = b * (kBlock * 4) + threadIdx.x;
-    uint32_t s[4];
+// ms[v] = MS id of its listed pair: rank_of[off[slot / kJV] + slot % kJV]
+// minus the field's first id, with slot = ms[v] on entry.  Runs over the chase
+// tiles, so every block knows its field.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_ms_final(Fields F, const uint32_t* off,
+                                                     const uint32_t* rank_of, const uint32_t* fbase) {
+    uint32_t tfirst, tlast;
+    block_tiles(F.dev_tiles ? F.dev_tiles[1] : F.j_tiles, &tfirst, &tlast);
+    for (uint32_t tile = tfirst; tile < tlast; ++tile) {
+        uint32_t fidx;
+        const FieldDesc fd = field_of_tile<false>(F, tile, &fidx);
+        const uint32_t lt = tile - fd.jbase;
+        const uint32_t base = fbase ? fbase[fd.index] : 0u;
+        uint32_t lv[kJPer], sl[kJPer];
+        bool ok[kJPer];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const uint32_t v = base + uint32_t(i) * kBlock;
-        s[i] = v < n ? uint32_t(ms[v]) : 0u;
+        for (int i = 0; i < kJPer; ++i) {
+            int x, y, z;
+            jtile_xyz<T>(fd, lt, threadIdx.x + i * kBlock, &x, &y, &z);
+            ok[i] = x < fd.nx && y < fd.ny && z < fd.nz;
+            lv[i] = (uint32_t(z) * uint32_t(fd.ny) + uint32_t(y)) * uint32_t(fd.nx) + uint32_t(x);
+            sl[i] = ok[i] ? uint32_t(fd.ms[lv[i]]) : 0u;
+        }
+#pragma unroll
+        for (int i = 0; i < kJPer; ++i)
+            if (ok[i]) fd.ms[lv[i]] = int32_t(rank_of[off[sl[i] / kJV] + sl[i] % kJV] - base);
     }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const uint32_t v = base + uint32_t(i) * kBlock;
-        if (v < n) ms[v] = int32_t(rank_of[off[s[i] / kJV] + s[i] % kJV]);
+}
+
+// First MS id of every field (pairs are sorted by launch-wide asc, so field
+// f's pairs start at the first key >= vbase_f << bn) and its K.  One block.
+__global__ __launch_bounds__(kBlock) void k_field_base(Fields F, const uint64_t* keys,
+                                                       const uint32_t* vals, const uint32_t* count_ptr,
+                                                       const uint32_t* k_total, const uint32_t* rank_of,
+                                                       int bn, uint32_t* fbase) {
+    const uint32_t nf = fields_count(F), count = *count_ptr;
+    for (uint32_t f = threadIdx.x; f < nf; f += kBlock) {
+        const FieldDesc fd = F.table ? F.table[f] : F.one;
+        const uint64_t target = uint64_t(fd.vbase) << bn;
+        uint32_t lo = 0, hi = count;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) / 2;
+            if (keys[mid] < target)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        fbase[f] = lo < count ? rank_of[vals[lo]] : *k_total;
+    }
+    __syncthreads();
+    for (uint32_t f = threadIdx.x; f < nf; f += kBlock) {
+        const FieldDesc fd = F.table ? F.table[f] : F.one;
+        const uint32_t next = f + 1 < nf ? fbase[f + 1] : *k_total;
+        if (fd.info) fd.info[3] = int32_t(next - fbase[f]);
+    }
+}
+
+// info[0..3] = 0 for every field of the launch.
+__global__ __launch_bounds__(kBlock) void k_init_fields(Fields F) {
+    const uint32_t nf = fields_count(F);
+    for (uint32_t f = blockIdx.x * kBlock + threadIdx.x; f < nf; f += gridDim.x * kBlock) {
+        const FieldDesc fd = F.table ? F.table[f] : F.one;
+        if (fd.info) {
+            fd.info[0] = 0;
+            fd.info[1] = 0;
+            fd.info[2] = 0;
+            fd.info[3] = 0;
+        }
     }
 }
 

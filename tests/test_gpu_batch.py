@@ -1,0 +1,157 @@
+"""GPU parity of the batched path: many fields of different sizes and shapes
+in one pass (and through replayable capacity plans) give, field by field, the
+oracle's labels, bit for bit, whatever their neighbours in the batch."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2303_15491_amd as plmss
+from paper_2303_15491_amd import fields
+from tests import bruteforce
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    return _t
+
+
+def _mixed_fields(seed=0):
+    rng = np.random.default_rng(seed)
+    shapes = [(20, 30, 70), (9, 8, 130), (50, 60), (300,), (16, 8, 64), (2, 2, 2), (1,), (1, 33), (33, 1, 17),
+              (5, 77, 1), (3, 3), (40, 41, 42)]
+    out = []
+    for i, sh in enumerate(shapes):
+        if len(sh) == 1 and sh[0] == 1:
+            out.append(np.array([0.5], np.float32))
+        else:
+            out.append(fields.smoothed_noise(sh, float(rng.uniform(1.0, 2.5)), seed=100 + i))
+    return out
+
+
+def _check_one(f, o, label):
+    ref = oracle.segment(f)
+    info = o["info"].cpu().numpy()
+    assert info[0] == 0, label
+    for k in ("asc", "desc", "ms"):
+        np.testing.assert_array_equal(o[k].cpu().numpy(), ref[k], err_msg=f"{label} {k}")
+    assert (info[1], info[2], info[3]) == (ref["n_min"], ref["n_max"], ref["K"]), label
+
+
+def test_batch_matches_oracle(torch):
+    fs = _mixed_fields()
+    _say(f"batch of {len(fs)} mixed fields")
+    outs = plmss.segment_batch([torch.from_numpy(f).cuda() for f in fs])
+    torch.cuda.synchronize()
+    for i, (f, o) in enumerate(zip(fs, outs)):
+        _check_one(f, o, f"field {i} {f.shape}")
+
+
+def test_batch_isolation_position_and_neighbours(torch):
+    fs = _mixed_fields(1)
+    target = fields.smoothed_noise((24, 33, 65), 1.5, seed=7)
+    alone = plmss.segment(torch.from_numpy(target).cuda())
+    for pos in (0, 5, len(fs)):
+        _say(f"isolation pos={pos}")
+        batch = fs[:pos] + [target] + fs[pos:]
+        outs = plmss.segment_batch([torch.from_numpy(f).cuda() for f in batch])
+        torch.cuda.synchronize()
+        for k in ("asc", "desc", "ms", "info"):
+            assert torch.equal(outs[pos][k], alone[k]), (pos, k)
+
+
+def test_batch_nan_stays_in_its_field(torch):
+    fs = _mixed_fields(2)
+    bad = fs[4].copy()
+    bad.ravel()[17] = np.nan
+    fs[4] = bad
+    _say("batch with a NaN field")
+    outs = plmss.segment_batch([torch.from_numpy(f).cuda() for f in fs])
+    torch.cuda.synchronize()
+    for i, (f, o) in enumerate(zip(fs, outs)):
+        if i == 4:
+            assert int(o["info"][0]) == plmss.E_NAN
+        else:
+            _check_one(f, o, f"field {i}")
+
+
+def test_batch_float64(torch):
+    fs = [f.astype(np.float64) for f in _mixed_fields(3)[:6]]
+    _say("float64 batch")
+    outs = plmss.segment_batch([torch.from_numpy(f).cuda() for f in fs])
+    torch.cuda.synchronize()
+    for i, (f, o) in enumerate(zip(fs, outs)):
+        _check_one(f, o, f"f64 field {i}")
+
+
+def test_uneven_batch_members(torch):
+    shapes = fields.batch_shapes(64, seed=4, lo=32, hi=192)[:6]
+    small = [tuple(max(8, s // 3) for s in sh) for sh in shapes]
+    fs = [fields.gaussian_blobs(sh, seed=4 + j) for j, sh in enumerate(small)]
+    _say(f"uneven batch {small}")
+    outs = plmss.segment_batch([torch.from_numpy(f).cuda() for f in fs])
+    torch.cuda.synchronize()
+    for i, (f, o) in enumerate(zip(fs, outs)):
+        _check_one(f, o, f"uneven {i} {f.shape}")
+
+
+def test_plan_graph_replays_different_batches(torch):
+    a = _mixed_fields(4)
+    b = [fields.smoothed_noise((30, 20, 10), 1.5, seed=9), fields.smoothed_noise((64, 64), 2.0, seed=10),
+         fields.smoothed_noise((7, 70, 9), 1.2, seed=11)]
+    da = [torch.from_numpy(f).cuda() for f in a]
+    db = [torch.from_numpy(f).cuda() for f in b]
+    need = [max(x, y) for x, y in zip(plmss.batch_needs(da), plmss.batch_needs(db))]
+    plan = plmss.Plan(need[0] + 1000, need[1] + 2, need[2] + 10, need[3] + 10)
+    for rnd, (fs, ds) in enumerate([(a, da), (b, db), (a, da), (b, db)]):
+        _say(f"plan replay {rnd}")
+        outs = plan.set(ds)
+        plan.launch(graph=True)
+        torch.cuda.synchronize()
+        for i, (f, o) in enumerate(zip(fs, outs)):
+            _check_one(f, o, f"replay {rnd} field {i}")
+        # eager work between replays
+        plmss.segment(da[0])
+        torch.cuda.synchronize()
+    outs = plan.set(db)
+    plan.launch(graph=False)
+    torch.cuda.synchronize()
+    for i, (f, o) in enumerate(zip(b, outs)):
+        _check_one(f, o, f"eager plan field {i}")
+    plan.close()
+
+
+def test_plan_rejects_batches_beyond_capacity(torch):
+    plan = plmss.Plan(1000, 2, 4, 4)
+    with pytest.raises(plmss.PlmssError) as e:
+        plan.set([torch.zeros(20, 20, 20, device="cuda")])
+    assert e.value.code == plmss.E_TOO_LARGE
+    plan.close()
+
+
+def test_grid3x3_orderings_in_one_batch(torch):
+    perms, asc, desc, ms, k = bruteforce.grid3x3_all_orderings()
+    rng = np.random.default_rng(3)
+    pick = rng.choice(perms.shape[0], 4000, replace=False)
+    fs = [torch.from_numpy(perms[i].astype(np.float32).reshape(3, 3)).cuda() for i in pick]
+    _say("3x3 orderings batch")
+    outs = plmss.segment_batch(fs)
+    torch.cuda.synchronize()
+    for j, i in enumerate(pick):
+        o = outs[j]
+        assert o["asc"].cpu().numpy().ravel().tolist() == asc[i].tolist()
+        assert o["desc"].cpu().numpy().ravel().tolist() == desc[i].tolist()
+        assert o["ms"].cpu().numpy().ravel().tolist() == ms[i].tolist()
+        assert int(o["info"][3]) == k[i]
