@@ -102,6 +102,84 @@ def per_kernel(launches, steps):
     return agg
 
 
+def bench_batched(torch, plmss, steps: int, warmup: int):
+    """The uneven batch (64 fields, sides 32..192): one plan launch (hipGraph)
+    against a loop of plain per-field calls that reads each field's K as a
+    caller would.  Both include everything from resident inputs to labels."""
+    from paper_2303_15491_amd import fields
+
+    log("generating the uneven batch")
+    host = fields.batch_fields(64, seed=4)
+    dev = [torch.from_numpy(f).cuda() for f in host]
+    nv = int(sum(f.size for f in host))
+    ws = torch.empty(max(plmss.workspace_bytes(t.shape) for t in dev), dtype=torch.uint8, device="cuda")
+    outs_plain = [{k: torch.empty(t.shape, dtype=torch.int32, device="cuda") for k in ("asc", "desc", "ms")}
+                  | {"info": torch.empty(4, dtype=torch.int32, device="cuda")} for t in dev]
+
+    def plain():
+        for t, o in zip(dev, outs_plain):
+            plmss.segment(t, workspace=ws, out=o)
+            int(o["info"][3].item())  # the caller reads K
+
+    needs = plmss.batch_needs(dev)
+    plan = plmss.Plan(*needs)
+    outs_b = plan.set(dev)
+
+    def batched():
+        plan.set(dev, outs=outs_b)
+        plan.launch(graph=True)
+        torch.cuda.synchronize()
+
+    for _ in range(warmup):
+        plain()
+        batched()
+    torch.cuda.synchronize()
+    same = all(torch.equal(a[k], b[k]) for a, b in zip(outs_plain, outs_b) for k in ("asc", "desc", "ms", "info"))
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plain()
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / steps
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        batched()
+    t_batch = (time.perf_counter() - t0) / steps
+    plan.close()
+    return {"workload": "64 fields, sides uniform in 32..192, sum of 16..256 Gaussians + N(0,0.02) (seeds 4+j)",
+            "vertices": nv, "batched_ms": t_batch * 1e3, "plain_loop_ms": t_plain * 1e3,
+            "batched_mvps": nv / t_batch / 1e6, "plain_loop_mvps": nv / t_plain / 1e6,
+            "speedup": t_plain / t_batch, "identical": bool(same)}
+
+
+def bench_serving(torch, plmss, n_requests: int, rate: float):
+    """Poisson arrivals of mixed 2-D (128^2..2048^2) and 3-D (64^3..384^3)
+    requests through the continuous-batching server, in real time."""
+    from paper_2303_15491_amd import fields
+    from paper_2303_15491_amd.serve import Server, run_trace
+
+    log("generating the serving pool")
+    pool_n = 64
+    _, pool_np = fields.serving_pool(pool_n, seed=5)
+    pool = [torch.from_numpy(f).pin_memory() for f in pool_np]
+    trace = fields.serving_trace(n_requests, seed=5, rate=rate)
+    sizes = [tuple(p.shape) for p in pool]
+    for i, req in enumerate(trace):  # every request is one of the pool's fields
+        req["shape"] = sizes[i % pool_n]
+    server = Server(budget_bytes=48 << 30, max_batch_vertices=64 << 20, max_batch_fields=32)
+    # warm-up: compile the graphs on a few requests
+    run_trace(server, trace[:16], lambda i, r: pool[i % pool_n], realtime=False)
+    server.done.clear()
+    log(f"serving {n_requests} requests at {rate}/s")
+    run_trace(server, trace, lambda i, r: pool[i % pool_n], realtime=True)
+    st = server.stats()
+    server.close()
+    offered = sum(int(np.prod(r["shape"])) for r in trace) / trace[-1]["t"] / 1e6
+    st.update({"rate_per_s": rate, "offered_mvps": offered,
+               "workload": "Poisson arrivals; half 2-D n^2 (n in 128..2048), half 3-D n^3 (n in 64..384), "
+                           "smoothed N(0,1) noise, sigma 1.5..4 (seed 5)"})
+    return st
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +188,9 @@ def main():
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--cpu-slab", type=int, default=128,
                     help="planes of the field the CPU oracle segments for the baseline (0 = skip)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the uneven-batch measurement")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="serving requests (0 = skip)")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -213,6 +294,10 @@ def main():
                          f"{t1 - t0:.2f} s", "host_cpu": model, "host_nproc": ncpu}
 
     labels_value = n / (ms_step_l * 1e-3) / 1e6
+    del ws, outs, field
+    torch.cuda.empty_cache()
+    batched = None if args.no_batched else bench_batched(torch, plmss, steps=max(3, args.steps // 2), warmup=2)
+    serving = bench_serving(torch, plmss, args.serve_requests, args.serve_rate) if args.serve_requests else None
     out = {
         "metric": METRIC, "value": value, "unit": "Mvertices/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
@@ -227,6 +312,8 @@ def main():
                         "note": "same labels, order field not materialised (vertex order compared in place)"},
         "kernels_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in sorted(kern.items())},
         "kernels_ms_per_step_labels_only": {k: round(v["ms_per_step"], 4) for k, v in sorted(kern_l.items())},
+        "batched": batched,
+        "serving": serving,
         "paper_context": "PLMSS Asc/Desc+MS on Miranda 512^3 (a different, simplified field): 57.6 Mvertices/s "
                          "on 24 Xeon SP 6126 cores, 3.36 on 1 core (Table 2)",
     }

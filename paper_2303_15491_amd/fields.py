@@ -135,3 +135,26 @@ def workload_c2(n: int = 256):
 def workload_c3(n: int = 512):
     """3-D n^3 noise smoothed at sigma 1.5 (seed 3); float32."""
     return smoothed_noise((n, n, n), 1.5, seed=3)
+
+
+def serving_pool(count: int = 64, seed: int = 5, sigmas=(1.5, 2.75, 4.0), max3d: int = 384, max2d: int = 2048):
+    """Host fields for the serving workload: ``count`` requests whose sizes
+    follow ``serving_trace(count, seed)``, each cut (at a seeded offset) from
+    one of a few smoothed-noise base fields -- the one whose sigma is nearest
+    the request's.  Crops of smoothed noise are smoothed noise, and cutting is
+    far cheaper than smoothing every request."""
+    trace = serving_trace(count, seed=seed)
+    rng = _rng(seed + 1)
+    base3 = {s: smoothed_noise((max3d,) * 3, s, seed=seed * 100 + i) for i, s in enumerate(sigmas)}
+    base2 = {s: smoothed_noise((max2d,) * 2, s, seed=seed * 100 + 50 + i) for i, s in enumerate(sigmas)}
+    out = []
+    for req in trace:
+        sig = min(sigmas, key=lambda s: abs(s - req["sigma"]))
+        base = base3[sig] if len(req["shape"]) == 3 else base2[sig]
+        sl = []
+        for n, m in zip(req["shape"], base.shape):
+            n = min(n, m)  # a request larger than the base is cut to the base
+            o = int(rng.integers(0, m - n + 1))
+            sl.append(slice(o, o + n))
+        out.append(np.ascontiguousarray(base[tuple(sl)]))
+    return trace, out
