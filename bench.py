@@ -25,15 +25,27 @@ sys.path.insert(0, ROOT)
 METRIC = "Mvertices/s full MS segmentation (bit-exact), batched vs plain; p99 ms"
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic HBM bytes per vertex of each kernel kind: every array the step
-# is defined on is read once and written once (float32 field, int32 labels).
-#   steepest : read order or f (4), write up, dn (8)
-#   jump     : read up, dn (8), write asc, desc (8)
-#   ms_final : read slot (4), write ms (4)
-ALGO_BYTES = {"steepest": 12.0, "jump": 16.0, "ms_final": 8.0}
-# One radix pass of (key, id) pairs reads and writes both (16 B); the first
-# pass reads only the field (4 + 8), the last writes only order[id] (8 + 4).
-RADIX_PASS_BYTES = 16.0
+# Algorithmic HBM bytes per vertex of one launch of each kernel kind: every
+# array the kernel is defined on is read once and written once (float32 field,
+# int32 labels, 32-bit keys).
+#   steepest      : read order or f (4), write up, dn (8)
+#   jump          : read up, dn (8), write asc, desc (8)
+#   ms_final      : read slot (4), write ms (4)
+#   order_first   : read f (4), write key, id (8)
+#   order_scatter : read key, id (8), write key, id (8)   (one middle radix pass)
+#   order_last    : read key, id (8), write sorted id (4)
+#   order_hist    : read key (4)
+#   order_invert  : read sorted ids (4), write order (4 / windows); with
+#                   windows = 0 it is the fused last pass: read key, id (8),
+#                   write order (4)
+ALGO_BYTES = {"steepest": 12.0, "jump": 16.0, "ms_final": 8.0, "order_first": 12.0, "order_scatter": 16.0,
+              "order_last": 12.0, "order_hist": 4.0}
+
+
+def algo_bytes(kind: str, windows: int):
+    if kind == "order_invert":
+        return 12.0 if windows == 0 else 4.0 + 4.0 / windows
+    return ALGO_BYTES.get(kind)
 
 
 def log(msg):
@@ -121,9 +133,17 @@ def bench_batched(torch, plmss, steps: int, warmup: int):
             plmss.segment(t, workspace=ws, out=o)
             int(o["info"][3].item())  # the caller reads K
 
+    from paper_2303_15491_amd import autotune
+
+    saved = plmss.tune_get()
+    tuned = autotune.tune_batch(dev, use_cache=False, log=log)
+    tuned.pop("trials", None)
     needs = plmss.batch_needs(dev)
     plan = plmss.Plan(*needs)
     outs_b = plan.set(dev)
+    plan.launch(graph=True)  # the graph keeps the tuned grids
+    torch.cuda.synchronize()
+    plmss.tune_set(**saved)  # the plain loop runs with the single-field settings
 
     def batched():
         plan.set(dev, outs=outs_b)
@@ -148,7 +168,7 @@ def bench_batched(torch, plmss, steps: int, warmup: int):
     return {"workload": "64 fields, sides uniform in 32..192, sum of 16..256 Gaussians + N(0,0.02) (seeds 4+j)",
             "vertices": nv, "batched_ms": t_batch * 1e3, "plain_loop_ms": t_plain * 1e3,
             "batched_mvps": nv / t_batch / 1e6, "plain_loop_mvps": nv / t_plain / 1e6,
-            "speedup": t_plain / t_batch, "identical": bool(same)}
+            "speedup": t_plain / t_batch, "identical": bool(same), "tuned": tuned}
 
 
 def bench_serving(torch, plmss, n_requests: int, rate: float):
@@ -239,6 +259,15 @@ def main():
     if not trace:
         raise RuntimeError("plmss_trace_create failed")
 
+    from paper_2303_15491_amd import autotune
+
+    log("autotuning launch shapes")
+    t_tune = time.perf_counter()
+    tuned = autotune.tune_segment(field, with_order=True, use_cache=False, log=log)
+    tuned["seconds"] = time.perf_counter() - t_tune
+    tuned.pop("trials", None)
+    knobs = plmss.tune_get()
+    log(f"tuned: {tuned}")
     log(f"warmup {args.warmup}")
     for _ in range(args.warmup):
         step_full()
@@ -263,12 +292,10 @@ def main():
     # roofline of the dominant kernel of the full step
     dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
     avg_ms = kern[dom]["avg_launch_ms"]
-    if dom in ALGO_BYTES:
-        per_launch_bytes = ALGO_BYTES[dom] * n
-        basis = f"{ALGO_BYTES[dom]:g} B/vertex x {n} vertices"
-    elif dom == "radix_scatter":
-        per_launch_bytes = RADIX_PASS_BYTES * n
-        basis = f"{RADIX_PASS_BYTES:g} B/vertex x {n} vertices (one radix pass)"
+    bpv = algo_bytes(dom, knobs["order_windows"])
+    if bpv is not None:
+        per_launch_bytes = bpv * n
+        basis = f"{bpv:g} B/vertex x {n} vertices per launch"
     else:
         per_launch_bytes = None
         basis = "n/a"
@@ -306,6 +333,7 @@ def main():
                    "parallelism": "single-gpu"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "tuned": tuned,
         "path_frac_of_hbm_roofline": n * 48.0 / (ms_step * 1e-3) / (HBM_PEAK_GBS * 1e9),
         "labels_only": {"value": labels_value, "ms_per_step": ms_step_l,
                         "path_frac_of_hbm_roofline": n * 48.0 / (ms_step_l * 1e-3) / (HBM_PEAK_GBS * 1e9),

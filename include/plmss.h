@@ -204,7 +204,12 @@ int plmss_plan_launch_graph(plmss_plan* plan, void* workspace, size_t workspace_
 #define PLMSS_KERNEL_COMPACT 7       /* MS pair compaction */
 #define PLMSS_KERNEL_RANK 8          /* MS pair ranking */
 #define PLMSS_KERNEL_MS_FINAL 9      /* MS id write-back */
-#define PLMSS_KERNEL_KINDS 10
+#define PLMSS_KERNEL_ORDER_HIST 10   /* order field: per-worker digit counts */
+#define PLMSS_KERNEL_ORDER_SCATTER 11 /* order field: middle passes, (key, id) to (key, id) */
+#define PLMSS_KERNEL_ORDER_INVERT 12 /* order field: order[id] = position */
+#define PLMSS_KERNEL_ORDER_FIRST 13  /* order field: first pass, field to (key, id) */
+#define PLMSS_KERNEL_ORDER_LAST 14   /* order field: last pass, (key, id) to sorted ids */
+#define PLMSS_KERNEL_KINDS 15
 
 typedef struct plmss_trace plmss_trace;
 plmss_trace* plmss_trace_create(int32_t max_launches);
@@ -213,6 +218,40 @@ int plmss_trace_begin(plmss_trace* trace);
 int plmss_trace_end(plmss_trace* trace);
 int32_t plmss_trace_read(plmss_trace* trace, int32_t* kinds, float* ms, int32_t max);
 const char* plmss_kernel_name(int32_t kind);
+
+/*
+ * Launch-shape knobs, for the autotuner.  Process-wide; a call reads them when
+ * it enqueues its kernels (a plan's hipGraph keeps the values it was captured
+ * with).  Results never depend on them, only speed does.
+ *   PLMSS_TUNE_ORDER_WORKERS   blocks of each order-field radix pass: 0 = one
+ *                              per 4096-key tile (default), or 64..65536, each
+ *                              block then owning a contiguous run of tiles.
+ *   PLMSS_TUNE_ORDER_WINDOWS   0 = the last order pass writes order[id] itself;
+ *                              w in 1..64 = it writes the sorted ids and w
+ *                              launches invert them, each for 1/w of the id
+ *                              range (default 2).
+ *   PLMSS_TUNE_SORT_WORKERS    blocks of device-sized sorts and scans (the MS
+ *                              pair sort): 64..4096, default 1024.
+ *   PLMSS_TUNE_PERSIST_BLOCKS  grid of a plan's persistent launches:
+ *                              64..16384, default 2048.
+ *   PLMSS_TUNE_SCAN_DEPTH      z-planes of a 3-D neighbour-scan tile (each
+ *                              block marches through that many planes of a
+ *                              64x8 column and compresses the paths inside
+ *                              it): 8, 16 (default) or 32.  A plan keeps the
+ *                              depth it was created with; plmss_batch_needs
+ *                              counts tiles with the current depth.
+ * plmss_tune_set returns PLMSS_OK, or PLMSS_E_ARG for an unknown knob or a
+ * value out of range (the knob is then unchanged).  plmss_tune_get returns the
+ * current value, or -1 for an unknown knob.
+ */
+#define PLMSS_TUNE_ORDER_WORKERS 0
+#define PLMSS_TUNE_ORDER_WINDOWS 1
+#define PLMSS_TUNE_SORT_WORKERS 2
+#define PLMSS_TUNE_PERSIST_BLOCKS 3
+#define PLMSS_TUNE_SCAN_DEPTH 4
+#define PLMSS_TUNE_KNOBS 5
+int32_t plmss_tune_set(int32_t knob, int64_t value);
+int64_t plmss_tune_get(int32_t knob);
 
 #ifdef __cplusplus
 }

@@ -14,7 +14,8 @@ import ctypes
 import os
 
 __all__ = ["PlmssError", "library", "segment", "order_field", "steepest", "compress", "ms_ids",
-           "segment_batch", "workspace_bytes", "batch_workspace_bytes", "batch_needs", "Plan"]
+           "segment_batch", "workspace_bytes", "batch_workspace_bytes", "batch_needs", "Plan",
+           "tune_get", "tune_set", "KNOBS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libplmss.so")
@@ -75,7 +76,12 @@ _SIGNATURES = {
     "plmss_trace_read": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float),
                           ctypes.c_int32], ctypes.c_int32),
     "plmss_kernel_name": ([ctypes.c_int32], ctypes.c_char_p),
+    "plmss_tune_set": ([ctypes.c_int32, ctypes.c_int64], ctypes.c_int32),
+    "plmss_tune_get": ([ctypes.c_int32], ctypes.c_int64),
 }
+
+# Launch-shape knobs (plmss_tune_*): name -> id.
+KNOBS = {"order_workers": 0, "order_windows": 1, "sort_workers": 2, "persist_blocks": 3, "scan_depth": 4}
 
 
 def library():
@@ -104,6 +110,21 @@ def _lib_status(code: int) -> str:
 def _check(rc: int, what: str):
     if rc != OK:
         raise PlmssError(rc, what)
+
+
+def tune_set(**values):
+    """Sets launch-shape knobs by name (see ``KNOBS``); results never change."""
+    lib = library()
+    for name, v in values.items():
+        if name not in KNOBS:
+            raise KeyError(name)
+        _check(lib.plmss_tune_set(KNOBS[name], int(v)), f"plmss_tune_set({name}={v})")
+
+
+def tune_get() -> dict:
+    """Current value of every launch-shape knob."""
+    lib = library()
+    return {name: int(lib.plmss_tune_get(k)) for name, k in KNOBS.items()}
 
 
 def _torch():

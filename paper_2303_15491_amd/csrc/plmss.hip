@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdint>
 #include <cstring>
 #include <new>
@@ -17,8 +18,27 @@ using namespace plmss;
 
 namespace {
 
-constexpr int64_t kMaxN = 2147483647;      // int32 labels
-constexpr unsigned kPersistBlocks = 2048;  // grid of capacity-sized (replayable) launches
+constexpr int64_t kMaxN = 2147483647;  // int32 labels
+
+// ---- launch-shape knobs (results never depend on them) ------------------------------
+struct KnobRange {
+    int64_t lo, hi, def;
+    bool zero_ok, pow2;
+};
+constexpr KnobRange kKnobs[PLMSS_TUNE_KNOBS] = {
+    {64, 1 << 16, 0, true, false},             // ORDER_WORKERS: 0 = one block per tile
+    {1, 64, 2, true, false},                   // ORDER_WINDOWS: 0 = fused inversion
+    {64, kMaxWorkers, kWorkers, false, false},  // SORT_WORKERS
+    {64, 16384, 2048, false, false},           // PERSIST_BLOCKS
+    {8, 32, 16, false, true},                  // SCAN_DEPTH: 8, 16 or 32 planes
+};
+std::atomic<int64_t> g_knob[PLMSS_TUNE_KNOBS] = {kKnobs[0].def, kKnobs[1].def, kKnobs[2].def,
+                                                 kKnobs[3].def, kKnobs[4].def};
+
+int64_t knob(int k) { return g_knob[k].load(std::memory_order_relaxed); }
+unsigned sort_workers() { return unsigned(knob(PLMSS_TUNE_SORT_WORKERS)); }
+unsigned persist_blocks() { return unsigned(knob(PLMSS_TUNE_PERSIST_BLOCKS)); }
+int scan_depth() { return int(knob(PLMSS_TUNE_SCAN_DEPTH)); }
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -46,13 +66,14 @@ int check_dims(const plmss_dims& d, uint64_t* n_out) {
 }
 
 // ---- shape classes ------------------------------------------------------------------
-// 3-D fields (nz > 1) use 64x8x16 scan tiles and 32x8x8 chase tiles; planar
-// fields (nz == 1) 64x16 and 64x32; lines (ny == nz == 1) 64x16 and 2048x1.
+// 3-D fields (nz > 1) use 64x8xZC scan tiles (ZC = the scan depth, 8, 16 or
+// 32 planes) and 32x8x8 chase tiles; planar fields (nz == 1) 64x16 and 64x32;
+// lines (ny == nz == 1) 64x16 and 2048x1.
 constexpr int kClasses = 3;
 int class_of(const plmss_dims& d) { return d.nz > 1 ? 0 : (d.ny > 1 ? 1 : 2); }
 
-uint32_t s_tiles_of(const plmss_dims& d) {
-    return class_of(d) == 0 ? steepest_tiles(d.nx, d.ny, d.nz, 8, 16) : steepest_tiles(d.nx, d.ny, d.nz, 16, 1);
+uint32_t s_tiles_of(const plmss_dims& d, int zc) {
+    return class_of(d) == 0 ? steepest_tiles(d.nx, d.ny, d.nz, 8, zc) : steepest_tiles(d.nx, d.ny, d.nz, 16, 1);
 }
 
 uint32_t j_tiles_of(const plmss_dims& d) {
@@ -73,9 +94,9 @@ struct Work {
     uint32_t* rank_of;   // u32[npad]: MS id of each listed pair (dense index)
     uint32_t* reg_cnt;   // u32[regions]: pairs listed per chase tile
     uint32_t* reg_off;   // u32[regions]: their exclusive prefix
-    uint32_t* hist;      // u32[kRadix * max(kWorkers, ntiles)]
+    uint32_t* hist;      // u32[kRadix * max(kMaxWorkers, ntiles)]
     uint32_t* dtotal;    // u32[kRadix]
-    uint32_t* partial;   // u32[kWorkers]
+    uint32_t* partial;   // u32[kMaxWorkers]
     uint32_t* counters;  // u32[64]: [0] = #pairs listed, [1] = K, [32..63] batch totals
     uint32_t* fbase;     // u32[nfields]: first MS id of each field
     FieldDesc* tables;   // batch tables: all fields, then one slot range per class
@@ -99,9 +120,9 @@ Sizes work_sizes(uint64_t nv, uint64_t regions, uint64_t nfields, uint64_t table
     s.vals = align_up(4 * s.npad, 256);
     s.rank = align_up(4 * s.npad, 256);
     s.regions = align_up(4 * std::max<uint64_t>(regions, 1), 256);
-    s.hist = align_up(size_t(4) * kRadix * std::max<uint64_t>(kWorkers, n_tiles(nv)), 256);
+    s.hist = align_up(size_t(4) * kRadix * std::max<uint64_t>(kMaxWorkers, n_tiles(nv)), 256);
     s.dtotal = align_up(4 * kRadix, 256);
-    s.partial = align_up(4 * kWorkers, 256);
+    s.partial = align_up(4 * kMaxWorkers, 256);
     s.counters = 256;
     s.fbase = align_up(4 * std::max<uint64_t>(nfields, 1), 256);
     s.tables = table_stride ? align_up(sizeof(FieldDesc) * 4 * table_stride, 256) : 0;
@@ -170,44 +191,71 @@ void launch(int kind, hipStream_t s, F&& f) {
 
 // ---- radix sort driver -------------------------------------------------------------------
 
+// Trace kinds of one radix pass: histogram, digit scan, scatter.
+struct PassKinds {
+    int hist, scan, scatter;
+};
+constexpr PassKinds kPairKinds{PLMSS_KERNEL_RADIX_HIST, PLMSS_KERNEL_RADIX_SCAN, PLMSS_KERNEL_RADIX_SCATTER};
+constexpr PassKinds kOrderKinds{PLMSS_KERNEL_ORDER_HIST, PLMSS_KERNEL_RADIX_SCAN, PLMSS_KERNEL_ORDER_SCATTER};
+
 // One pass over `workers` blocks; cnt (device) or n (host) is the length.
 template <class Src, class Dst>
 void radix_pass(Src src, Dst dst, const uint32_t* cnt, uint32_t n, unsigned workers, int shift,
-                bool check_nan, const Work& w, int32_t* info, hipStream_t s) {
+                bool check_nan, const Work& w, int32_t* info, hipStream_t s, PassKinds kinds = kPairKinds,
+                int scatter_kind = -1) {
     if (check_nan)
-        launch(PLMSS_KERNEL_RADIX_HIST, s, [&] {
+        launch(kinds.hist, s, [&] {
             k_radix_hist<Src, true><<<workers, kBlock, 0, s>>>(src, cnt, n, shift, w.hist, info);
         });
     else
-        launch(PLMSS_KERNEL_RADIX_HIST, s, [&] {
+        launch(kinds.hist, s, [&] {
             k_radix_hist<Src, false><<<workers, kBlock, 0, s>>>(src, cnt, n, shift, w.hist, info);
         });
-    launch(PLMSS_KERNEL_RADIX_SCAN, s, [&] {
+    launch(kinds.scan, s, [&] {
         k_radix_digit_scan<<<kRadix, kBlock, 0, s>>>(w.hist, w.dtotal, int(workers));
     });
-    launch(PLMSS_KERNEL_RADIX_SCATTER, s, [&] {
+    launch(scatter_kind >= 0 ? scatter_kind : kinds.scatter, s, [&] {
         k_radix_scatter<Src, Dst><<<workers, kBlock, 0, s>>>(src, dst, cnt, n, shift, w.hist, w.dtotal);
     });
 }
 
-// Order field of a float field: keys from the values, values = ids; the last
-// pass writes order[id] = position.  One worker per tile.
+// Order field of a float field: keys from the values, values = ids.  The last
+// pass either writes order[id] = position itself (scattered 4-byte writes over
+// the whole order array) or writes the sorted ids, which k_invert then turns
+// into order[] one id window at a time.
 template <typename T, typename K>
 void sort_order(const T* f, uint32_t n, int32_t* order, const Work& w, int32_t* info,
                 hipStream_t s) {
     constexpr int passes = int(sizeof(K)) * 8 / kRadixBits;
-    const unsigned workers = unsigned(n_tiles(n));
+    const unsigned tiles = unsigned(n_tiles(n));
+    const int64_t kw = knob(PLMSS_TUNE_ORDER_WORKERS);
+    const unsigned workers = kw == 0 ? tiles : unsigned(std::min<int64_t>(kw, tiles));
+    const int64_t windows = knob(PLMSS_TUNE_ORDER_WINDOWS);
     K* keys[2] = {reinterpret_cast<K*>(w.keys[0]), reinterpret_cast<K*>(w.keys[1])};
     FieldSrc<T, K> first{f};
-    radix_pass(first, ArrayDst<K>{keys[0], w.vals[0]}, nullptr, n, workers, 0, true, w, info, s);
+    radix_pass(first, ArrayDst<K>{keys[0], w.vals[0]}, nullptr, n, workers, 0, true, w, info, s, kOrderKinds,
+               PLMSS_KERNEL_ORDER_FIRST);
     int cur = 0;
     for (int p = 1; p < passes - 1; ++p) {
         radix_pass(ArraySrc<K>{keys[cur], w.vals[cur]}, ArrayDst<K>{keys[cur ^ 1], w.vals[cur ^ 1]},
-                   nullptr, n, workers, kRadixBits * p, false, w, info, s);
+                   nullptr, n, workers, kRadixBits * p, false, w, info, s, kOrderKinds);
         cur ^= 1;
     }
-    radix_pass(ArraySrc<K>{keys[cur], w.vals[cur]}, RankDst<K>{order}, nullptr, n, workers,
-               kRadixBits * (passes - 1), false, w, info, s);
+    const int last = kRadixBits * (passes - 1);
+    if (windows == 0) {
+        radix_pass(ArraySrc<K>{keys[cur], w.vals[cur]}, RankDst<K>{order}, nullptr, n, workers, last, false, w,
+                   info, s, kOrderKinds, PLMSS_KERNEL_ORDER_INVERT);
+        return;
+    }
+    uint32_t* ids = w.vals[cur ^ 1];
+    radix_pass(ArraySrc<K>{keys[cur], w.vals[cur]}, IdDst<K>{ids}, nullptr, n, workers, last, false, w, info, s,
+               kOrderKinds, PLMSS_KERNEL_ORDER_LAST);
+    const uint32_t span = uint32_t((uint64_t(n) + uint64_t(windows) - 1) / uint64_t(windows));
+    for (uint64_t lo = 0; lo < n; lo += span) {
+        const uint32_t hi = uint32_t(std::min<uint64_t>(n, lo + span));
+        launch(PLMSS_KERNEL_ORDER_INVERT, s,
+               [&] { k_invert<<<tiles, kBlock, 0, s>>>(ids, n, uint32_t(lo), hi, order); });
+    }
 }
 
 void order_any(const void* field, int32_t dtype, uint32_t n, int32_t* order, const Work& w,
@@ -227,7 +275,7 @@ int sort_pairs(int bits, const Work& w, hipStream_t s) {
     int cur = 0;
     for (int p = 0; p < passes; ++p) {
         radix_pass(ArraySrc<uint64_t>{keys[cur], w.vals[cur]},
-                   ArrayDst<uint64_t>{keys[cur ^ 1], w.vals[cur ^ 1]}, w.counters, 0, kWorkers,
+                   ArrayDst<uint64_t>{keys[cur ^ 1], w.vals[cur ^ 1]}, w.counters, 0, sort_workers(),
                    kRadixBits * p, false, w, nullptr, s);
         cur ^= 1;
     }
@@ -237,9 +285,10 @@ int sort_pairs(int bits, const Work& w, hipStream_t s) {
 // Exclusive prefix of in[0..m) into out; m from m_dev when given.
 void prefix_sum(const uint32_t* in, const uint32_t* m_dev, uint32_t m, uint32_t* out,
                 uint32_t* total, const Work& w, hipStream_t s) {
-    launch(PLMSS_KERNEL_PREFIX, s, [&] { k_sum_reduce<<<kWorkers, kBlock, 0, s>>>(in, m_dev, m, w.partial); });
-    launch(PLMSS_KERNEL_PREFIX, s, [&] { k_scan_partials<<<1, kBlock, 0, s>>>(w.partial, kWorkers, total); });
-    launch(PLMSS_KERNEL_PREFIX, s, [&] { k_scan_apply<<<kWorkers, kBlock, 0, s>>>(in, m_dev, m, w.partial, out); });
+    const unsigned nw = sort_workers();
+    launch(PLMSS_KERNEL_PREFIX, s, [&] { k_sum_reduce<<<nw, kBlock, 0, s>>>(in, m_dev, m, w.partial); });
+    launch(PLMSS_KERNEL_PREFIX, s, [&] { k_scan_partials<<<1, kBlock, 0, s>>>(w.partial, int(nw), total); });
+    launch(PLMSS_KERNEL_PREFIX, s, [&] { k_scan_apply<<<nw, kBlock, 0, s>>>(in, m_dev, m, w.partial, out); });
 }
 
 // ---- one launch over a set of fields -------------------------------------------------------
@@ -256,28 +305,35 @@ struct LaunchSet {
     bool capacity;                // grids sized for a capacity, totals on the device
     int bn;
     int32_t dtype;
+    int zc;                       // scan depth of the 3-D scan tiles
 };
 
+// zc: the scan depth the tile counts of F were computed with.
 template <bool RESOLVE, class Src>
-void launch_steepest_cls(int c, const Fields& F, unsigned grid, uint32_t* up, uint32_t* dn, hipStream_t s) {
+void launch_steepest_cls(int c, int zc, const Fields& F, unsigned grid, uint32_t* up, uint32_t* dn,
+                         hipStream_t s) {
     if (grid == 0) return;
     launch(PLMSS_KERNEL_STEEPEST, s, [&] {
-        if (c == 0)
-            k_steepest<Src, 8, 16, RESOLVE><<<grid, kBlock, 0, s>>>(F, up, dn);
-        else
+        if (c != 0)
             k_steepest<Src, 16, 1, RESOLVE><<<grid, kBlock, 0, s>>>(F, up, dn);
+        else if (zc == 8)
+            k_steepest<Src, 8, 8, RESOLVE><<<grid, kBlock, 0, s>>>(F, up, dn);
+        else if (zc == 32)
+            k_steepest<Src, 8, 32, RESOLVE><<<grid, kBlock, 0, s>>>(F, up, dn);
+        else
+            k_steepest<Src, 8, 16, RESOLVE><<<grid, kBlock, 0, s>>>(F, up, dn);
     });
 }
 
 template <bool RESOLVE>
-void launch_steepest_any(int c, const Fields& F, unsigned grid, int32_t dtype, bool order, uint32_t* up,
-                         uint32_t* dn, hipStream_t s) {
+void launch_steepest_any(int c, int zc, const Fields& F, unsigned grid, int32_t dtype, bool order,
+                         uint32_t* up, uint32_t* dn, hipStream_t s) {
     if (order)
-        launch_steepest_cls<RESOLVE, RankOrder>(c, F, grid, up, dn, s);
+        launch_steepest_cls<RESOLVE, RankOrder>(c, zc, F, grid, up, dn, s);
     else if (dtype == PLMSS_F32)
-        launch_steepest_cls<RESOLVE, FieldOrder<float, uint32_t>>(c, F, grid, up, dn, s);
+        launch_steepest_cls<RESOLVE, FieldOrder<float, uint32_t>>(c, zc, F, grid, up, dn, s);
     else
-        launch_steepest_cls<RESOLVE, FieldOrder<double, uint64_t>>(c, F, grid, up, dn, s);
+        launch_steepest_cls<RESOLVE, FieldOrder<double, uint64_t>>(c, zc, F, grid, up, dn, s);
 }
 
 template <bool CHASE>
@@ -312,17 +368,18 @@ void launch_ms_final_cls(int c, const Fields& F, unsigned grid, const Work& w, h
 void ms_from_pairs(const LaunchSet& L, const Work& w, hipStream_t s) {
     uint64_t* rec = reinterpret_cast<uint64_t*>(w.keys[1]);
     prefix_sum(w.reg_cnt, L.regions_dev, L.regions, w.reg_off, w.counters + 0, w, s);
-    const unsigned cgrid = L.capacity ? kPersistBlocks : std::max(1u, L.regions);
+    const unsigned cgrid = L.capacity ? persist_blocks() : std::max(1u, L.regions);
     launch(PLMSS_KERNEL_COMPACT, s, [&] {
         k_compact_pairs<<<cgrid, kBlock, 0, s>>>(w.reg_cnt, w.reg_off, L.regions_dev, L.regions, rec,
                                                  reinterpret_cast<uint64_t*>(w.keys[0]), w.vals[0]);
     });
     const int r = sort_pairs(2 * L.bn, w, s);
     const uint64_t* sk = reinterpret_cast<const uint64_t*>(w.keys[r]);
-    launch(PLMSS_KERNEL_RANK, s, [&] { k_rank_reduce<<<kWorkers, kBlock, 0, s>>>(sk, w.counters + 0, w.partial); });
-    launch(PLMSS_KERNEL_PREFIX, s, [&] { k_scan_partials<<<1, kBlock, 0, s>>>(w.partial, kWorkers, w.counters + 1); });
+    const unsigned nw = sort_workers();
+    launch(PLMSS_KERNEL_RANK, s, [&] { k_rank_reduce<<<nw, kBlock, 0, s>>>(sk, w.counters + 0, w.partial); });
+    launch(PLMSS_KERNEL_PREFIX, s, [&] { k_scan_partials<<<1, kBlock, 0, s>>>(w.partial, int(nw), w.counters + 1); });
     launch(PLMSS_KERNEL_RANK, s, [&] {
-        k_rank_apply<<<kWorkers, kBlock, 0, s>>>(sk, w.vals[r], w.counters + 0, w.partial, w.rank_of);
+        k_rank_apply<<<nw, kBlock, 0, s>>>(sk, w.vals[r], w.counters + 0, w.partial, w.rank_of);
     });
     launch(PLMSS_KERNEL_RANK, s, [&] {
         k_field_base<<<1, kBlock, 0, s>>>(L.all, sk, w.vals[r], w.counters + 0, w.counters + 1, w.rank_of,
@@ -345,7 +402,7 @@ void run_set(const LaunchSet& L, const void* field, int32_t* order, uint32_t n_s
         if (L.used[c]) {
             Fields F = L.cls[c];
             if (order) F.one.src = order;
-            launch_steepest_any<true>(c, F, L.grid_s[c], L.dtype, order != nullptr, U, D, s);
+            launch_steepest_any<true>(c, L.zc, F, L.grid_s[c], L.dtype, order != nullptr, U, D, s);
         }
     for (int c = 0; c < kClasses; ++c)
         if (L.used[c]) launch_chase_cls<true>(c, L.cls[c], L.grid_j[c], U, D, L.bn, w, s);
@@ -382,10 +439,11 @@ Fields fields_one(const FieldDesc& d, uint32_t s_tiles, uint32_t j_tiles) {
 }
 
 // A single field: everything passed by value, one block per tile.
-LaunchSet single_set(const plmss_job& job, uint64_t n) {
+LaunchSet single_set(const plmss_job& job, uint64_t n, int zc) {
     LaunchSet L{};
+    L.zc = zc;
     const int c = class_of(job.dims);
-    const uint32_t st = s_tiles_of(job.dims), jt = j_tiles_of(job.dims);
+    const uint32_t st = s_tiles_of(job.dims, zc), jt = j_tiles_of(job.dims);
     const FieldDesc d = desc_of(job, 0, 0, 0);
     L.all = fields_one(d, st, jt);
     for (int k = 0; k < kClasses; ++k) L.used[k] = false;
@@ -407,9 +465,11 @@ struct BatchLayout {
     std::vector<FieldDesc> all, cls[kClasses];
     uint32_t s_tiles[kClasses] = {0, 0, 0}, j_tiles[kClasses] = {0, 0, 0}, region0[kClasses] = {0, 0, 0};
     uint64_t nv = 0, regions = 0;
+    int zc = 16;
 };
 
-int batch_layout(int32_t n_jobs, const plmss_job* jobs, BatchLayout* B) {
+int batch_layout(int32_t n_jobs, const plmss_job* jobs, int zc, BatchLayout* B) {
+    B->zc = zc;
     if (n_jobs < 1 || !jobs) return PLMSS_E_ARG;
     const int32_t dtype = jobs[0].dtype;
     std::vector<uint64_t> nvert(n_jobs);
@@ -430,7 +490,7 @@ int batch_layout(int32_t n_jobs, const plmss_job* jobs, BatchLayout* B) {
         B->all.push_back(d);
         B->cls[c].push_back(d);
         vb += uint32_t(nvert[i]);
-        B->s_tiles[c] += s_tiles_of(jobs[i].dims);
+        B->s_tiles[c] += s_tiles_of(jobs[i].dims, zc);
         B->j_tiles[c] += j_tiles_of(jobs[i].dims);
     }
     // pair-list regions: class 0 tiles first, then class 1, then class 2
@@ -473,6 +533,7 @@ LaunchSet batch_set(const BatchLayout& B, const FieldDesc* tables, size_t stride
     L.capacity = false;
     L.bn = bn;
     L.dtype = dtype;
+    L.zc = B.zc;
     return L;
 }
 
@@ -483,7 +544,7 @@ LaunchSet batch_set(const BatchLayout& B, const FieldDesc* tables, size_t stride
 constexpr int kTot = 32;
 
 LaunchSet capacity_set(const Work& w, size_t stride, unsigned grid_s, unsigned grid_j, uint32_t max_regions,
-                       int32_t dtype, int bn) {
+                       int32_t dtype, int bn, int zc) {
     const uint32_t* tot = w.counters + kTot;
     LaunchSet L{};
     L.all = Fields{};
@@ -505,6 +566,7 @@ LaunchSet capacity_set(const Work& w, size_t stride, unsigned grid_s, unsigned g
     L.capacity = true;
     L.bn = bn;
     L.dtype = dtype;
+    L.zc = zc;
     return L;
 }
 
@@ -519,6 +581,7 @@ struct plmss_plan {
     int64_t max_chase_tiles = 0;
     int32_t dtype = 0;
     int bn = 1;
+    int zc = 16;  // scan depth, fixed at creation: tables and launches agree
     Sizes sizes{};
     FieldDesc* pinned = nullptr;     // host staging of the tables
     uint32_t* pinned_tot = nullptr;  // host staging of the totals
@@ -568,7 +631,7 @@ int plmss_segment(const plmss_job* job, void* workspace, size_t workspace_bytes,
     if (!ws_ok(workspace, workspace_bytes, sz.total)) return PLMSS_E_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const Work w = carve(workspace, sz);
-    const LaunchSet L = single_set(*job, n);
+    const LaunchSet L = single_set(*job, n, scan_depth());
     run_set(L, job->field, job->order, uint32_t(n), w, s);
     return launch_status();
 }
@@ -605,8 +668,9 @@ int plmss_steepest(const void* field, const int32_t* order, plmss_dims dims, int
     j.field = order ? static_cast<const void*>(order) : field;
     j.dims = dims;
     j.info = info;
-    const Fields F = fields_one(desc_of(j, 0, 0, 0), s_tiles_of(dims), j_tiles_of(dims));
-    launch_steepest_any<false>(class_of(dims), F, s_tiles_of(dims), order ? PLMSS_F32 : dtype,
+    const int zc = scan_depth();
+    const Fields F = fields_one(desc_of(j, 0, 0, 0), s_tiles_of(dims, zc), j_tiles_of(dims));
+    launch_steepest_any<false>(class_of(dims), zc, F, s_tiles_of(dims, zc), order ? PLMSS_F32 : dtype,
                                order != nullptr, reinterpret_cast<uint32_t*>(up),
                                reinterpret_cast<uint32_t*>(dn), s);
     return launch_status();
@@ -644,7 +708,7 @@ int plmss_ms_ids(const int32_t* asc, const int32_t* desc, int64_t n, int32_t* ms
     j.desc = const_cast<int32_t*>(desc);
     j.ms = ms;
     j.info = info;
-    const LaunchSet L = single_set(j, uint64_t(n));
+    const LaunchSet L = single_set(j, uint64_t(n), scan_depth());
     launch(PLMSS_KERNEL_MISC, s, [&] { k_init<<<1, 64, 0, s>>>(info, w.counters, 8); });
     launch_chase_cls<false>(class_of(d), L.cls[class_of(d)], L.grid_j[class_of(d)], nullptr, nullptr, L.bn, w, s);
     ms_from_pairs(L, w, s);
@@ -653,14 +717,14 @@ int plmss_ms_ids(const int32_t* asc, const int32_t* desc, int64_t n, int32_t* ms
 
 size_t plmss_batch_workspace_bytes(int32_t n_jobs, const plmss_job* jobs) {
     BatchLayout B;
-    if (batch_layout(n_jobs, jobs, &B) != PLMSS_OK) return 0;
+    if (batch_layout(n_jobs, jobs, scan_depth(), &B) != PLMSS_OK) return 0;
     return work_sizes(B.nv, B.regions, uint64_t(n_jobs), uint64_t(n_jobs)).total;
 }
 
 int plmss_segment_batch(int32_t n_jobs, const plmss_job* jobs, void* workspace,
                         size_t workspace_bytes, void* stream) {
     BatchLayout B;
-    int rc = batch_layout(n_jobs, jobs, &B);
+    int rc = batch_layout(n_jobs, jobs, scan_depth(), &B);
     if (rc) return rc;
     const Sizes sz = work_sizes(B.nv, B.regions, uint64_t(n_jobs), uint64_t(n_jobs));
     if (!ws_ok(workspace, workspace_bytes, sz.total)) return PLMSS_E_WORKSPACE;
@@ -680,7 +744,7 @@ int plmss_segment_batch(int32_t n_jobs, const plmss_job* jobs, void* workspace,
 int32_t plmss_batch_needs(int32_t n_jobs, const plmss_job* jobs, int64_t* needs) {
     if (!needs) return PLMSS_E_ARG;
     BatchLayout B;
-    int rc = batch_layout(n_jobs, jobs, &B);
+    int rc = batch_layout(n_jobs, jobs, scan_depth(), &B);
     if (rc) return rc;
     needs[0] = int64_t(B.nv);
     needs[1] = n_jobs;
@@ -703,6 +767,7 @@ plmss_plan* plmss_plan_create(int64_t max_vertices, int32_t max_fields, int64_t 
     p->max_chase_tiles = max_chase_tiles;
     p->dtype = dtype;
     p->bn = id_bits(uint64_t(max_vertices));
+    p->zc = scan_depth();
     p->sizes = work_sizes(uint64_t(max_vertices), uint64_t(max_chase_tiles), uint64_t(max_fields),
                           uint64_t(max_fields));
     if (hipHostMalloc(reinterpret_cast<void**>(&p->pinned), sizeof(FieldDesc) * 4 * size_t(max_fields)) !=
@@ -733,7 +798,7 @@ int plmss_plan_set(plmss_plan* p, int32_t n_jobs, const plmss_job* jobs, void* w
                    size_t workspace_bytes, void* stream) {
     if (!p) return PLMSS_E_ARG;
     BatchLayout B;
-    int rc = batch_layout(n_jobs, jobs, &B);
+    int rc = batch_layout(n_jobs, jobs, p->zc, &B);
     if (rc) return rc;
     if (jobs[0].dtype != p->dtype) return PLMSS_E_ARG;
     if (n_jobs > p->max_fields || B.nv > uint64_t(p->max_vertices) ||
@@ -770,9 +835,10 @@ int plmss_plan_launch(plmss_plan* p, void* workspace, size_t workspace_bytes, vo
     if (!ws_ok(workspace, workspace_bytes, p->sizes.total)) return PLMSS_E_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const Work w = carve(workspace, p->sizes);
-    const unsigned gs = unsigned(std::min<int64_t>(kPersistBlocks, p->max_scan_tiles));
-    const unsigned gj = unsigned(std::min<int64_t>(kPersistBlocks, p->max_chase_tiles));
-    const LaunchSet L = capacity_set(w, size_t(p->max_fields), gs, gj, uint32_t(p->max_chase_tiles), p->dtype, p->bn);
+    const unsigned gs = unsigned(std::min<int64_t>(persist_blocks(), p->max_scan_tiles));
+    const unsigned gj = unsigned(std::min<int64_t>(persist_blocks(), p->max_chase_tiles));
+    const LaunchSet L =
+        capacity_set(w, size_t(p->max_fields), gs, gj, uint32_t(p->max_chase_tiles), p->dtype, p->bn, p->zc);
     run_set(L, nullptr, nullptr, 0, w, s);
     return launch_status();
 }
@@ -882,9 +948,26 @@ int32_t plmss_trace_read(plmss_trace* tr, int32_t* kinds, float* ms, int32_t max
 
 const char* plmss_kernel_name(int32_t kind) {
     static const char* names[PLMSS_KERNEL_KINDS] = {
-        "misc", "radix_hist", "radix_digit_scan", "radix_scatter", "steepest",
-        "jump", "prefix_sum", "pair_compact", "pair_rank", "ms_final"};
+        "misc", "radix_hist", "radix_digit_scan", "radix_scatter", "steepest", "jump", "prefix_sum",
+        "pair_compact", "pair_rank", "ms_final", "order_hist", "order_scatter", "order_invert",
+        "order_first", "order_last"};
     return (kind >= 0 && kind < PLMSS_KERNEL_KINDS) ? names[kind] : "unknown";
+}
+
+// ---- launch-shape knobs -------------------------------------------------------------------
+
+int32_t plmss_tune_set(int32_t knob_id, int64_t value) {
+    if (knob_id < 0 || knob_id >= PLMSS_TUNE_KNOBS) return PLMSS_E_ARG;
+    const KnobRange& r = kKnobs[knob_id];
+    if (!(value == 0 && r.zero_ok) && (value < r.lo || value > r.hi)) return PLMSS_E_ARG;
+    if (r.pow2 && (value & (value - 1)) != 0) return PLMSS_E_ARG;
+    g_knob[knob_id].store(value, std::memory_order_relaxed);
+    return PLMSS_OK;
+}
+
+int64_t plmss_tune_get(int32_t knob_id) {
+    if (knob_id < 0 || knob_id >= PLMSS_TUNE_KNOBS) return -1;
+    return knob(knob_id);
 }
 
 }  // extern "C"

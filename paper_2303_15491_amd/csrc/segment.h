@@ -2,6 +2,8 @@
 // cross-tile chase, MS-pair listing, compaction and ranking.
 #pragma once
 
+#include <type_traits>
+
 #include "common.h"
 #include "sort.h"
 
@@ -405,20 +407,21 @@ __global__ __launch_bounds__(kBlock) void k_steepest(Fields F, uint32_t* up, uin
         // entries of this thread: (lz, row) pairs over the tile's planes; entry
         // e has local index li0 + (e / RPW) * TY * kTX + (e % RPW) * kTX
         constexpr int kMine = ZC * RPW;
-        static_assert(kMine <= 32, "one mask bit per entry");
+        static_assert(kMine <= 64, "one mask bit per entry");
+        using Mask = typename std::conditional<(kMine > 32), uint64_t, uint32_t>::type;
         const int nz_t = z1 - z0;
         const int li0 = (w * RPW) * kTX + lane;
-        uint32_t todo = 0;
+        Mask todo = 0;
 #pragma unroll
         for (int e = 0; e < kMine; ++e) {
             const int lz = e / RPW, ly = w * RPW + e % RPW;
-            if (lz < nz_t && x < g.nx && y0 + ly < g.ny) todo |= 1u << e;
+            if (lz < nz_t && x < g.nx && y0 + ly < g.ny) todo |= Mask(1) << e;
         }
         // in-place rounds of p <- p[p]; an entry is finished once both of its
         // pointers reach an exit vertex or a root.  The loop over entries is
         // uniform; an entry no lane of the wave still needs is skipped.
         auto step = [&](int e, bool& ch) {
-            const bool mine = (todo >> e) & 1u;
+            const bool mine = (todo >> e) & Mask(1);
             if (!__ballot(mine)) return;
             const int li = li0 + (e / RPW) * (TY * kTX) + (e % RPW) * kTX;
             const uint32_t own = lp[li];
@@ -430,7 +433,7 @@ __global__ __launch_bounds__(kBlock) void k_steepest(Fields F, uint32_t* up, uin
             // an entry has one owner, so rewriting an unchanged value is harmless
             lp[li] = nu | (nd << 16);
             ch |= (nu != pu) || (nd != pd);
-            todo &= (su && sd) ? ~(1u << e) : ~0u;
+            todo &= (su && sd) ? ~(Mask(1) << e) : ~Mask(0);
         };
         // sweeps alternate direction, so chains of either orientation compress
         // in one sweep when their entries happen to lie in sweep order.  A few

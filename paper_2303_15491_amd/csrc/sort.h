@@ -20,7 +20,8 @@ constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;  // == kBlock: one thread per digit
 constexpr int kItems = 16;               // keys per thread per tile
 constexpr int kTile = kBlock * kItems;
-constexpr int kWorkers = 1024;           // grid of device-sized sorts and scans
+constexpr int kWorkers = 1024;           // default grid of device-sized sorts and scans
+constexpr int kMaxWorkers = 4096;        // largest such grid (sizes the workspace)
 static_assert(kRadix == kBlock, "one thread per digit");
 
 __device__ __forceinline__ uint32_t load_count(const uint32_t* count_ptr, uint32_t n) {
@@ -81,6 +82,14 @@ struct RankDst {
     }
 };
 
+// Last pass of the order field when the inversion runs separately: only the
+// vertex ids, in sorted order.
+template <typename K>
+struct IdDst {
+    uint32_t* ids;
+    __device__ __forceinline__ void put(uint32_t pos, K, uint32_t v) const { ids[pos] = v; }
+};
+
 template <typename K>
 __device__ __forceinline__ uint32_t digit_of(K k, int shift) {
     return uint32_t(k >> shift) & (kRadix - 1);
@@ -97,6 +106,9 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
     }
     return peers;
 }
+
+// Highest lane of a non-empty lane set.
+__device__ __forceinline__ int top_lane(uint64_t m) { return 63 - __clzll(static_cast<long long>(m)); }
 
 // ---- kernels -----------------------------------------------------------------------
 
@@ -204,19 +216,26 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(Src src, Dst dst,
             val[i] = idx < hi ? src.val(idx) : 0u;
         }
         __syncthreads();
-        uint32_t local[kItems];
+        // rank inside the wave: the highest lane of each digit group adds the
+        // group's size to the wave's counter and gets the count before it;
+        // the adds of all rows are issued back to back (LDS keeps a wave's
+        // operations in order), then each group reads its leader's result
+        uint32_t local[kItems], val_tmp[kItems];
+        int leader[kItems];
 #pragma unroll
         for (int i = 0; i < kItems; ++i) {
             const uint32_t idx = wbase + uint32_t(i) * kWave;
             const bool valid = idx < hi;
             const uint32_t d = digit_of(key[i], shift);
             const uint64_t peers = match_digit(d, valid);
+            leader[i] = peers ? top_lane(peers) : lane;
+            local[i] = uint32_t(__popcll(peers & lt));
             uint32_t prior = 0;
-            if (valid) prior = sm.wcnt[w][d];
-            local[i] = prior + uint32_t(__popcll(peers & lt));
-            // the highest peer lane publishes the new count for this digit
-            if (valid && (peers >> lane) == 1ull) sm.wcnt[w][d] = prior + uint32_t(__popcll(peers));
+            if (valid && leader[i] == lane) prior = atomicAdd(&sm.wcnt[w][d], uint32_t(__popcll(peers)));
+            val_tmp[i] = prior;
         }
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) local[i] += uint32_t(__shfl(int(val_tmp[i]), leader[i]));
         __syncthreads();
         {
             uint32_t c[kWavesPerBlock], sum = 0;
@@ -257,6 +276,25 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(Src src, Dst dst,
         }
         __syncthreads();
         sm.run[t] += sm.tcount[t];
+    }
+}
+
+// order[ids[i]] = i for the ids in [lo, hi): the inversion of the sorted ids,
+// restricted to one window of the id range so that the scattered writes of
+// one launch stay within a region the memory-side cache can hold.
+__global__ __launch_bounds__(kBlock) void k_invert(const uint32_t* ids, uint32_t n, uint32_t lo,
+                                                   uint32_t hi, int32_t* order) {
+    const uint32_t base = blockIdx.x * uint32_t(kTile) + threadIdx.x;
+    uint32_t v[kItems];
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        const uint32_t j = base + uint32_t(i) * kBlock;
+        v[i] = j < n ? ids[j] : 0xffffffffu;
+    }
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        const uint32_t j = base + uint32_t(i) * kBlock;
+        if (v[i] - lo < hi - lo) order[v[i]] = int32_t(j);
     }
 }
 

@@ -93,3 +93,26 @@ def test_python_binding_refuses_host_tensors():
     torch = pytest.importorskip("torch")
     with pytest.raises(ValueError):
         plmss.segment(torch.zeros(4, 4))
+
+
+def test_tuning_knobs_validate_ranges():
+    saved = plmss.tune_get()
+    lib = plmss.library()
+    try:
+        assert set(saved) == set(plmss.KNOBS)
+        assert lib.plmss_tune_get(99) == -1
+        assert lib.plmss_tune_set(99, 1) == plmss.E_ARG
+        assert lib.plmss_tune_set(plmss.KNOBS["sort_workers"], 0) == plmss.E_ARG
+        assert lib.plmss_tune_set(plmss.KNOBS["sort_workers"], 5000) == plmss.E_ARG
+        assert lib.plmss_tune_get(plmss.KNOBS["sort_workers"]) == saved["sort_workers"]
+        assert lib.plmss_tune_set(plmss.KNOBS["scan_depth"], 24) == plmss.E_ARG
+        assert lib.plmss_tune_set(plmss.KNOBS["scan_depth"], 64) == plmss.E_ARG
+        plmss.tune_set(order_workers=0, order_windows=0, sort_workers=512, persist_blocks=4096, scan_depth=8)
+        assert plmss.tune_get() == {"order_workers": 0, "order_windows": 0, "sort_workers": 512,
+                                    "persist_blocks": 4096, "scan_depth": 8}
+        with pytest.raises(plmss.PlmssError):
+            plmss.tune_set(order_workers=10)
+        with pytest.raises(KeyError):
+            plmss.tune_set(nothing=1)
+    finally:
+        plmss.tune_set(**saved)

@@ -83,6 +83,23 @@ def test_ragged_tiles_both_paths(torch, shape):
         assert torch.equal(a[k], b[k])
 
 
+@pytest.mark.parametrize("knobs", [
+    {"scan_depth": 8}, {"scan_depth": 32}, {"order_windows": 0}, {"order_windows": 3, "order_workers": 64},
+    {"order_windows": 64, "order_workers": 4096}, {"sort_workers": 64}, {"sort_workers": 4096},
+])
+def test_launch_shapes_keep_results(torch, knobs):
+    """Every launch-shape knob setting gives the oracle's labels (tile depths
+    that split a field unevenly, ragged last windows, one-tile workers)."""
+    saved = plmss.tune_get()
+    try:
+        plmss.tune_set(**knobs)
+        f = fields.smoothed_noise((45, 70, 130), 1.5, seed=5)
+        _compare_full(torch, f, True, f"knobs {knobs}")
+        _compare_full(torch, fields.smoothed_noise((40, 1, 33), 2.0, seed=6), True, f"knobs {knobs} thin")
+    finally:
+        plmss.tune_set(**saved)
+
+
 def test_degenerate_dims(torch):
     _compare_full(torch, np.arange(1000, dtype=np.float32), True, "line")
     _compare_full(torch, np.array([1.5], np.float32), True, "single")
