@@ -31,20 +31,24 @@ HBM_PEAK_GBS = 8000.0
 #   steepest      : read order or f (4), write up, dn (8)
 #   jump          : read up, dn (8), write asc, desc (8)
 #   ms_final      : read slot (4), write ms (4)
-#   order_first   : read f (4), write key, id (8)
-#   order_scatter : read key, id (8), write key, id (8)   (one middle radix pass)
-#   order_last    : read key, id (8), write sorted id (4)
+#   order_first   : read f (4), write key and id (8)
+#   order_scatter : read key and id (8), write key and id (8)  (a middle pass)
+#   order_last    : read key and id (8); write (id, position) grouped by id
+#                   range (8) [order_invert = 1] or the sorted id (4) [>= 2]
+#   order_invert  : read (id, position) (8), write order (4) [order_invert = 1];
+#                   the fused last pass: read key and id (8), write order (4)
+#                   [0]; read sorted ids (4), write order (4 / w) [w >= 2]
+#   order_regroup : read (id, position) (8), write it regrouped by id chunk (8)
 #   order_hist    : read key (4)
-#   order_invert  : read sorted ids (4), write order (4 / windows); with
-#                   windows = 0 it is the fused last pass: read key, id (8),
-#                   write order (4)
 ALGO_BYTES = {"steepest": 12.0, "jump": 16.0, "ms_final": 8.0, "order_first": 12.0, "order_scatter": 16.0,
-              "order_last": 12.0, "order_hist": 4.0}
+              "order_hist": 4.0, "order_regroup": 16.0}
 
 
-def algo_bytes(kind: str, windows: int):
+def algo_bytes(kind: str, invert: int):
+    if kind == "order_last":
+        return 16.0 if invert == 1 else 12.0
     if kind == "order_invert":
-        return 12.0 if windows == 0 else 4.0 + 4.0 / windows
+        return 12.0 if invert in (0, 1) else 4.0 + 4.0 / invert
     return ALGO_BYTES.get(kind)
 
 
@@ -211,6 +215,10 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the uneven-batch measurement")
     ap.add_argument("--serve-requests", type=int, default=2000, help="serving requests (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--knobs", default=None,
+                    help='launch-shape knobs as JSON (e.g. {"scan_depth": 8}); skips the autotuner')
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 1 GiB device to device three times (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -223,6 +231,15 @@ def main():
 
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": src.numel() * 4, "copy_probe_bytes_written": dst.numel() * 4,
+                          "launches": 3}))
+        return
     lib = plmss.library()
     log(f"generating workload {args.workload}")
     f_host, desc = workload(args.workload)
@@ -261,11 +278,15 @@ def main():
 
     from paper_2303_15491_amd import autotune
 
-    log("autotuning launch shapes")
-    t_tune = time.perf_counter()
-    tuned = autotune.tune_segment(field, with_order=True, use_cache=False, log=log)
-    tuned["seconds"] = time.perf_counter() - t_tune
-    tuned.pop("trials", None)
+    if args.knobs:
+        plmss.tune_set(**json.loads(args.knobs))
+        tuned = {"knobs": plmss.tune_get(), "given": True}
+    else:
+        log("autotuning launch shapes")
+        t_tune = time.perf_counter()
+        tuned = autotune.tune_segment(field, with_order=True, use_cache=False, log=log)
+        tuned["seconds"] = time.perf_counter() - t_tune
+        tuned.pop("trials", None)
     knobs = plmss.tune_get()
     log(f"tuned: {tuned}")
     log(f"warmup {args.warmup}")
@@ -292,7 +313,7 @@ def main():
     # roofline of the dominant kernel of the full step
     dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
     avg_ms = kern[dom]["avg_launch_ms"]
-    bpv = algo_bytes(dom, knobs["order_windows"])
+    bpv = algo_bytes(dom, knobs["order_invert"])
     if bpv is not None:
         per_launch_bytes = bpv * n
         basis = f"{bpv:g} B/vertex x {n} vertices per launch"

@@ -208,8 +208,9 @@ int plmss_plan_launch_graph(plmss_plan* plan, void* workspace, size_t workspace_
 #define PLMSS_KERNEL_ORDER_SCATTER 11 /* order field: middle passes, (key, id) to (key, id) */
 #define PLMSS_KERNEL_ORDER_INVERT 12 /* order field: order[id] = position */
 #define PLMSS_KERNEL_ORDER_FIRST 13  /* order field: first pass, field to (key, id) */
-#define PLMSS_KERNEL_ORDER_LAST 14   /* order field: last pass, (key, id) to sorted ids */
-#define PLMSS_KERNEL_KINDS 15
+#define PLMSS_KERNEL_ORDER_LAST 14   /* order field: last pass (sorted ids, or (id, position) by range) */
+#define PLMSS_KERNEL_ORDER_REGROUP 15 /* order field: (id, position) regrouped by id chunk */
+#define PLMSS_KERNEL_KINDS 16
 
 typedef struct plmss_trace plmss_trace;
 plmss_trace* plmss_trace_create(int32_t max_launches);
@@ -224,12 +225,21 @@ const char* plmss_kernel_name(int32_t kind);
  * it enqueues its kernels (a plan's hipGraph keeps the values it was captured
  * with).  Results never depend on them, only speed does.
  *   PLMSS_TUNE_ORDER_WORKERS   blocks of each order-field radix pass: 0 = one
- *                              per 4096-key tile (default), or 64..65536, each
- *                              block then owning a contiguous run of tiles.
- *   PLMSS_TUNE_ORDER_WINDOWS   0 = the last order pass writes order[id] itself;
- *                              w in 1..64 = it writes the sorted ids and w
- *                              launches invert them, each for 1/w of the id
- *                              range (default 2).
+ *                              per 4096-key tile, or 64..65536 (default
+ *                              8192), each block then owning a contiguous run
+ *                              of tiles.
+ *   PLMSS_TUNE_ORDER_INVERT    how order[id] = position is written: 0 = by the
+ *                              last radix pass itself (scattered writes over
+ *                              the whole array); 1 (default) = the last pass
+ *                              groups (id, position) pairs by id range, a
+ *                              second launch regroups them by chunks of 32768
+ *                              ids and a third inverts each chunk in LDS and
+ *                              writes it as one coalesced run; w in
+ *                              2..64 = the last pass writes the sorted ids and
+ *                              w launches invert them, each for 1/w of the id
+ *                              range.
+ *   PLMSS_TUNE_ORDER_PACKED    1 (default) = 32-bit keys travel packed with
+ *                              their ids in one 64-bit word; 0 = two arrays.
  *   PLMSS_TUNE_SORT_WORKERS    blocks of device-sized sorts and scans (the MS
  *                              pair sort): 64..4096, default 1024.
  *   PLMSS_TUNE_PERSIST_BLOCKS  grid of a plan's persistent launches:
@@ -245,11 +255,12 @@ const char* plmss_kernel_name(int32_t kind);
  * current value, or -1 for an unknown knob.
  */
 #define PLMSS_TUNE_ORDER_WORKERS 0
-#define PLMSS_TUNE_ORDER_WINDOWS 1
+#define PLMSS_TUNE_ORDER_INVERT 1
 #define PLMSS_TUNE_SORT_WORKERS 2
 #define PLMSS_TUNE_PERSIST_BLOCKS 3
 #define PLMSS_TUNE_SCAN_DEPTH 4
-#define PLMSS_TUNE_KNOBS 5
+#define PLMSS_TUNE_ORDER_PACKED 5
+#define PLMSS_TUNE_KNOBS 6
 int32_t plmss_tune_set(int32_t knob, int64_t value);
 int64_t plmss_tune_get(int32_t knob);
 

@@ -21,6 +21,15 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nblocks) {
     return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + k;
 }
 
+// Pointers that reach a kernel inside a descriptor (not as a kernel argument)
+// are generic to the compiler, which then emits flat memory instructions; flat
+// accesses also count against the LDS wait counter, so every LDS wait would
+// wait for them too.  Device data lives in global memory: say so.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
+    return (__attribute__((address_space(1))) T*)p;
+}
+
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 __device__ __forceinline__ int wave_id() { return threadIdx.x / kWave; }
 

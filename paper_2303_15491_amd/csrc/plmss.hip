@@ -26,14 +26,15 @@ struct KnobRange {
     bool zero_ok, pow2;
 };
 constexpr KnobRange kKnobs[PLMSS_TUNE_KNOBS] = {
-    {64, 1 << 16, 0, true, false},             // ORDER_WORKERS: 0 = one block per tile
-    {1, 64, 2, true, false},                   // ORDER_WINDOWS: 0 = fused inversion
+    {64, 1 << 16, 8192, true, false},          // ORDER_WORKERS: 0 = one block per tile
+    {1, 64, 1, true, false},                   // ORDER_INVERT: 0 fused, 1 id ranges, 2.. windows
     {64, kMaxWorkers, kWorkers, false, false},  // SORT_WORKERS
     {64, 16384, 2048, false, false},           // PERSIST_BLOCKS
     {8, 32, 16, false, true},                  // SCAN_DEPTH: 8, 16 or 32 planes
+    {1, 1, 1, true, false},                    // ORDER_PACKED: 32-bit keys packed with ids
 };
 std::atomic<int64_t> g_knob[PLMSS_TUNE_KNOBS] = {kKnobs[0].def, kKnobs[1].def, kKnobs[2].def,
-                                                 kKnobs[3].def, kKnobs[4].def};
+                                                 kKnobs[3].def, kKnobs[4].def, kKnobs[5].def};
 
 int64_t knob(int k) { return g_knob[k].load(std::memory_order_relaxed); }
 unsigned sort_workers() { return unsigned(knob(PLMSS_TUNE_SORT_WORKERS)); }
@@ -98,15 +99,20 @@ struct Work {
     uint32_t* dtotal;    // u32[kRadix]
     uint32_t* partial;   // u32[kMaxWorkers]
     uint32_t* counters;  // u32[64]: [0] = #pairs listed, [1] = K, [32..63] batch totals
+    uint32_t* sortaux;   // u32[kSortAux]: order sort, id-range totals and chunk fill counters
     uint32_t* fbase;     // u32[nfields]: first MS id of each field
     FieldDesc* tables;   // batch tables: all fields, then one slot range per class
     uint64_t npad;
 };
 
 struct Sizes {
-    size_t keys, vals, rank, regions, hist, dtotal, partial, counters, fbase, tables, total;
+    size_t keys, vals, rank, regions, hist, dtotal, partial, counters, sortaux, fbase, tables, total;
     uint64_t npad;
 };
+
+// Order-sort bookkeeping: totals of the id ranges, then one fill counter per
+// id chunk (at most 2^31 / kChunk).
+constexpr size_t kSortAux = kRadix + (size_t(1) << (31 - kChunkBits));
 
 uint64_t n_tiles(uint64_t n) { return (n + kTile - 1) / kTile; }
 
@@ -124,10 +130,11 @@ Sizes work_sizes(uint64_t nv, uint64_t regions, uint64_t nfields, uint64_t table
     s.dtotal = align_up(4 * kRadix, 256);
     s.partial = align_up(4 * kMaxWorkers, 256);
     s.counters = 256;
+    s.sortaux = align_up(4 * kSortAux, 256);
     s.fbase = align_up(4 * std::max<uint64_t>(nfields, 1), 256);
     s.tables = table_stride ? align_up(sizeof(FieldDesc) * 4 * table_stride, 256) : 0;
     s.total = 2 * s.keys + 2 * s.vals + s.rank + 2 * s.regions + s.hist + s.dtotal + s.partial +
-              s.counters + s.fbase + s.tables;
+              s.counters + s.sortaux + s.fbase + s.tables;
     return s;
 }
 
@@ -150,6 +157,7 @@ Work carve(void* ws, const Sizes& s) {
     w.dtotal = reinterpret_cast<uint32_t*>(take(s.dtotal));
     w.partial = reinterpret_cast<uint32_t*>(take(s.partial));
     w.counters = reinterpret_cast<uint32_t*>(take(s.counters));
+    w.sortaux = reinterpret_cast<uint32_t*>(take(s.sortaux));
     w.fbase = reinterpret_cast<uint32_t*>(take(s.fbase));
     w.tables = s.tables ? reinterpret_cast<FieldDesc*>(take(s.tables)) : nullptr;
     w.npad = s.npad;
@@ -219,43 +227,120 @@ void radix_pass(Src src, Dst dst, const uint32_t* cnt, uint32_t n, unsigned work
     });
 }
 
-// Order field of a float field: keys from the values, values = ids.  The last
-// pass either writes order[id] = position itself (scattered 4-byte writes over
-// the whole order array) or writes the sorted ids, which k_invert then turns
-// into order[] one id window at a time.
-template <typename T, typename K>
-void sort_order(const T* f, uint32_t n, int32_t* order, const Work& w, int32_t* info,
-                hipStream_t s) {
+// Ping-pong storage of the order sort's (key, id) items: 32-bit keys packed
+// with their ids in one word, or keys and ids in two arrays.
+struct PackedItems {
+    uint64_t* kv[2];
+    uint32_t* ids_buf;
+    PackedSrc src(int c) const { return {kv[c]}; }
+    PackedDst dst(int c) const { return {kv[c]}; }
+    uint64_t* spare(int c) const { return kv[c ^ 1]; }
+    uint64_t* own(int c) const { return kv[c]; }
+    uint32_t* ids(int) const { return ids_buf; }
+};
+
+template <typename K>
+struct SplitItems {
+    K* keys[2];
+    uint32_t* vals[2];
+    ArraySrc<K> src(int c) const { return {keys[c], vals[c]}; }
+    ArrayDst<K> dst(int c) const { return {keys[c], vals[c]}; }
+    uint64_t* spare(int c) const { return reinterpret_cast<uint64_t*>(keys[c ^ 1]); }
+    uint64_t* own(int c) const { return reinterpret_cast<uint64_t*>(keys[c]); }
+    uint32_t* ids(int c) const { return vals[c ^ 1]; }
+};
+
+// Order field of a float field: an LSD radix sort of (key, id) with keys from
+// the values, then order[id] = position, written in one of three ways
+// (PLMSS_TUNE_ORDER_INVERT): fused into the last pass (scattered writes over
+// the whole order array); by id chunk (the last pass writes (id, position)
+// grouped by id range, k_chunk_partition regroups them by chunk of kChunk
+// ids, k_invert_chunks inverts each chunk in LDS); or as sorted ids inverted
+// by `windows` launches over parts of the id range.
+template <typename T, typename K, class Items>
+void sort_order_items(const T* f, uint32_t n, int32_t* order, const Work& w, int32_t* info, hipStream_t s,
+                      const Items& it) {
     constexpr int passes = int(sizeof(K)) * 8 / kRadixBits;
     const unsigned tiles = unsigned(n_tiles(n));
     const int64_t kw = knob(PLMSS_TUNE_ORDER_WORKERS);
     const unsigned workers = kw == 0 ? tiles : unsigned(std::min<int64_t>(kw, tiles));
-    const int64_t windows = knob(PLMSS_TUNE_ORDER_WINDOWS);
-    K* keys[2] = {reinterpret_cast<K*>(w.keys[0]), reinterpret_cast<K*>(w.keys[1])};
-    FieldSrc<T, K> first{f};
-    radix_pass(first, ArrayDst<K>{keys[0], w.vals[0]}, nullptr, n, workers, 0, true, w, info, s, kOrderKinds,
+    const int64_t inv = knob(PLMSS_TUNE_ORDER_INVERT);
+    radix_pass(FieldSrc<T, K>{f}, it.dst(0), nullptr, n, workers, 0, true, w, info, s, kOrderKinds,
                PLMSS_KERNEL_ORDER_FIRST);
     int cur = 0;
     for (int p = 1; p < passes - 1; ++p) {
-        radix_pass(ArraySrc<K>{keys[cur], w.vals[cur]}, ArrayDst<K>{keys[cur ^ 1], w.vals[cur ^ 1]},
-                   nullptr, n, workers, kRadixBits * p, false, w, info, s, kOrderKinds);
+        radix_pass(it.src(cur), it.dst(cur ^ 1), nullptr, n, workers, kRadixBits * p, false, w, info, s,
+                   kOrderKinds);
         cur ^= 1;
     }
     const int last = kRadixBits * (passes - 1);
-    if (windows == 0) {
-        radix_pass(ArraySrc<K>{keys[cur], w.vals[cur]}, RankDst<K>{order}, nullptr, n, workers, last, false, w,
-                   info, s, kOrderKinds, PLMSS_KERNEL_ORDER_INVERT);
+    const auto src = it.src(cur);
+    using Src = decltype(it.src(0));
+    if (inv == 0) {
+        radix_pass(src, RankDst<K>{order}, nullptr, n, workers, last, false, w, info, s, kOrderKinds,
+                   PLMSS_KERNEL_ORDER_INVERT);
         return;
     }
-    uint32_t* ids = w.vals[cur ^ 1];
-    radix_pass(ArraySrc<K>{keys[cur], w.vals[cur]}, IdDst<K>{ids}, nullptr, n, workers, last, false, w, info, s,
-               kOrderKinds, PLMSS_KERNEL_ORDER_LAST);
-    const uint32_t span = uint32_t((uint64_t(n) + uint64_t(windows) - 1) / uint64_t(windows));
+    if (inv == 1) {
+        // id ranges of 1 to 256 chunks, at most 64 of them below 2^29
+        // vertices (longer write runs) and 256 above; ihist (256 x workers <=
+        // npad entries) in rank_of, which the order sort does not otherwise use
+        const int id_shift =
+            std::min(kChunkBits + 8, std::max(kChunkBits, bit_width(uint64_t(n) - 1) - 6));
+        uint32_t* ihist = w.rank_of;
+        uint32_t* itotal = w.sortaux;
+        uint32_t* chunk_fill = w.sortaux + kRadix;
+        const uint32_t chunks = uint32_t((uint64_t(n) + kChunk - 1) / kChunk);
+        uint64_t* parts = it.spare(cur);
+        uint64_t* parts2 = it.own(cur);  // free once the last pass has read it
+        launch(PLMSS_KERNEL_ORDER_HIST, s, [&] {
+            k_radix_hist<Src, false, true><<<workers, kBlock, 0, s>>>(src, nullptr, n, last, w.hist, info, id_shift,
+                                                                      ihist);
+        });
+        launch(PLMSS_KERNEL_RADIX_SCAN, s, [&] {
+            k_radix_digit_scan<<<kRadix, kBlock, 0, s>>>(w.hist, w.dtotal, int(workers));
+        });
+        launch(PLMSS_KERNEL_RADIX_SCAN, s, [&] {
+            k_radix_digit_scan<<<kRadix, kBlock, 0, s>>>(ihist, itotal, int(workers));
+        });
+        launch(PLMSS_KERNEL_ORDER_LAST, s, [&] {
+            k_rank_partition<Src><<<workers, kBlock, 0, s>>>(src, n, last, w.hist, w.dtotal, ihist, itotal,
+                                                             id_shift, parts);
+        });
+        launch(PLMSS_KERNEL_MISC, s, [&] {
+            k_zero_u32<<<std::min(256u, (chunks + kBlock - 1) / kBlock), kBlock, 0, s>>>(chunk_fill, chunks);
+        });
+        launch(PLMSS_KERNEL_ORDER_REGROUP, s, [&] {
+            k_chunk_partition<<<tiles, kBlock, 0, s>>>(parts, n, id_shift, chunk_fill, parts2);
+        });
+        launch(PLMSS_KERNEL_ORDER_INVERT, s,
+               [&] { k_invert_chunks<<<chunks, kInvertBlock, 0, s>>>(parts2, n, order); });
+        return;
+    }
+    uint32_t* ids = it.ids(cur);
+    radix_pass(src, IdDst<K>{ids}, nullptr, n, workers, last, false, w, info, s, kOrderKinds,
+               PLMSS_KERNEL_ORDER_LAST);
+    const uint32_t span = uint32_t((uint64_t(n) + uint64_t(inv) - 1) / uint64_t(inv));
     for (uint64_t lo = 0; lo < n; lo += span) {
         const uint32_t hi = uint32_t(std::min<uint64_t>(n, lo + span));
         launch(PLMSS_KERNEL_ORDER_INVERT, s,
                [&] { k_invert<<<tiles, kBlock, 0, s>>>(ids, n, uint32_t(lo), hi, order); });
     }
+}
+
+template <typename T, typename K>
+void sort_order(const T* f, uint32_t n, int32_t* order, const Work& w, int32_t* info, hipStream_t s) {
+    if constexpr (sizeof(K) == 4) {
+        if (knob(PLMSS_TUNE_ORDER_PACKED) != 0) {
+            const PackedItems it{{reinterpret_cast<uint64_t*>(w.keys[0]), reinterpret_cast<uint64_t*>(w.keys[1])},
+                                 w.vals[1]};
+            sort_order_items<T, K>(f, n, order, w, info, s, it);
+            return;
+        }
+    }
+    const SplitItems<K> it{{reinterpret_cast<K*>(w.keys[0]), reinterpret_cast<K*>(w.keys[1])},
+                           {w.vals[0], w.vals[1]}};
+    sort_order_items<T, K>(f, n, order, w, info, s, it);
 }
 
 void order_any(const void* field, int32_t dtype, uint32_t n, int32_t* order, const Work& w,
@@ -950,7 +1035,7 @@ const char* plmss_kernel_name(int32_t kind) {
     static const char* names[PLMSS_KERNEL_KINDS] = {
         "misc", "radix_hist", "radix_digit_scan", "radix_scatter", "steepest", "jump", "prefix_sum",
         "pair_compact", "pair_rank", "ms_final", "order_hist", "order_scatter", "order_invert",
-        "order_first", "order_last"};
+        "order_first", "order_last", "order_regroup"};
     return (kind >= 0 && kind < PLMSS_KERNEL_KINDS) ? names[kind] : "unknown";
 }
 

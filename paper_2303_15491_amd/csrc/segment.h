@@ -13,14 +13,17 @@ namespace plmss {
 
 // The order of a float field under the paper's tie rule, compared through
 // order-preserving integer keys (vertex ids break ties, see below).
+// fetch() issues the load; key() turns the loaded value into the key, so
+// that loads can stay in flight while other work runs.
 template <typename T, typename K>
 struct FieldOrder {
     using key_t = K;
+    using raw_t = T;
     static constexpr bool kCheckNan = true;
     const T* f;
     static __device__ __forceinline__ FieldOrder from(const void* p) { return {static_cast<const T*>(p)}; }
-    __device__ __forceinline__ K load(size_t i, bool& nan) const {
-        const T a = f[i];
+    __device__ __forceinline__ T fetch(size_t i) const { return gmem(f)[i]; }
+    static __device__ __forceinline__ K key(T a, bool& nan) {
         nan |= is_nan(a);
         return sos_key(a);
     }
@@ -30,10 +33,12 @@ struct FieldOrder {
 // below every vertex (it marks grid positions outside the field).
 struct RankOrder {
     using key_t = uint32_t;
+    using raw_t = int32_t;
     static constexpr bool kCheckNan = false;
     const int32_t* order;
     static __device__ __forceinline__ RankOrder from(const void* p) { return {static_cast<const int32_t*>(p)}; }
-    __device__ __forceinline__ uint32_t load(size_t i, bool&) const { return uint32_t(order[i]) + 1u; }
+    __device__ __forceinline__ int32_t fetch(size_t i) const { return gmem(order)[i]; }
+    static __device__ __forceinline__ uint32_t key(int32_t a, bool&) { return uint32_t(a) + 1u; }
 };
 
 struct GridDims {
@@ -68,12 +73,37 @@ struct Fields {
     FieldDesc one;
 };
 
+// A descriptor read from a device table (member by member: the table lives
+// in global memory, and a struct copy cannot bind across address spaces).
+__device__ __forceinline__ FieldDesc load_desc(const FieldDesc* table, uint32_t f) {
+    const auto* g = gmem(table) + f;
+    FieldDesc d;
+    d.src = g->src;
+    d.asc = g->asc;
+    d.desc = g->desc;
+    d.ms = g->ms;
+    d.info = g->info;
+    d.nx = g->nx;
+    d.ny = g->ny;
+    d.nz = g->nz;
+    d.vbase = g->vbase;
+    d.sbase = g->sbase;
+    d.jbase = g->jbase;
+    d.index = g->index;
+    return d;
+}
+
+// Descriptor of field f of the launch.
+__device__ __forceinline__ FieldDesc field_desc(const Fields& F, uint32_t f) {
+    return F.table ? load_desc(F.table, f) : F.one;
+}
+
 __device__ __forceinline__ uint32_t fields_region0(const Fields& F) {
-    return F.dev_tiles ? F.dev_tiles[3] : F.region0;
+    return F.dev_tiles ? gmem(F.dev_tiles)[3] : F.region0;
 }
 
 __device__ __forceinline__ uint32_t fields_count(const Fields& F) {
-    return F.dev_tiles ? F.dev_tiles[2] : (F.table ? F.n : 1u);
+    return F.dev_tiles ? gmem(F.dev_tiles)[2] : (F.table ? F.n : 1u);
 }
 
 // Field owning launch-wide tile `tile` (by sbase when STEEP, else jbase).
@@ -86,14 +116,14 @@ __device__ __forceinline__ FieldDesc field_of_tile(const Fields& F, uint32_t til
     uint32_t lo = 0, hi = fields_count(F);
     while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) / 2;
-        const uint32_t b = STEEP ? F.table[mid].sbase : F.table[mid].jbase;
+        const uint32_t b = STEEP ? gmem(F.table)[mid].sbase : gmem(F.table)[mid].jbase;
         if (b <= tile)
             lo = mid;
         else
             hi = mid;
     }
     *index = lo;
-    return F.table[lo];
+    return load_desc(F.table, lo);
 }
 
 // This block's tiles: a contiguous run, so that each XCD works on a compact
@@ -222,7 +252,7 @@ __global__ __launch_bounds__(kBlock) void k_steepest(Fields F, uint32_t* up, uin
     __shared__ int nan_seen;
     const int t = threadIdx.x, w = wave_id(), lane = lane_id();
     uint32_t tfirst, tlast;
-    block_tiles(F.dev_tiles ? F.dev_tiles[0] : F.s_tiles, &tfirst, &tlast);
+    block_tiles(F.dev_tiles ? gmem(F.dev_tiles)[0] : F.s_tiles, &tfirst, &tlast);
     for (uint32_t tile = tfirst; tile < tlast; ++tile) {
     uint32_t fidx;
     const FieldDesc fd = field_of_tile<true>(F, tile, &fidx);
@@ -260,20 +290,21 @@ __global__ __launch_bounds__(kBlock) void k_steepest(Fields F, uint32_t* up, uin
         ld_off[k] = in ? int64_t(gy) * int64_t(sx) + gx : -1;
     }
     bool nan = false;
-    // plane loads go through registers so that the next plane's loads are in
-    // flight while the current plane is computed
-    K pre[kLoads];
+    // plane loads go through registers as raw values, so that the next
+    // plane's loads are in flight while the current plane is computed; the
+    // key transform waits until the plane is stored
+    using R = typename Src::raw_t;
+    R pre[kLoads];
     auto fetch_plane = [&](int z) {
         const size_t zb = size_t(z) * sxy;
 #pragma unroll
-        for (int k = 0; k < kLoads; ++k)
-            pre[k] = ld_off[k] >= 0 ? src.load(zb + size_t(ld_off[k]), nan) : K(0);
+        for (int k = 0; k < kLoads; ++k) pre[k] = ld_off[k] >= 0 ? src.fetch(zb + size_t(ld_off[k])) : R(0);
     };
     auto store_plane = [&](int slot) {
         K* dst = &pl[kSquares ? 0 : slot][0][0];
 #pragma unroll
         for (int k = 0; k < kLoads; ++k)
-            if (ld_slot[k] >= 0) dst[ld_slot[k]] = pre[k];
+            if (ld_slot[k] >= 0) dst[ld_slot[k]] = ld_off[k] >= 0 ? Src::key(pre[k], nan) : K(0);
     };
     auto load_plane = [&](int slot, int z) {
         fetch_plane(z);
@@ -557,7 +588,7 @@ __global__ __launch_bounds__(kBlock) void k_chase(Fields F, uint32_t* U, uint32_
     __shared__ uint32_t tmp[kWavesPerBlock];
     const int t = threadIdx.x, lane = lane_id(), w = wave_id();
     uint32_t tfirst, tlast;
-    block_tiles(F.dev_tiles ? F.dev_tiles[1] : F.j_tiles, &tfirst, &tlast);
+    block_tiles(F.dev_tiles ? gmem(F.dev_tiles)[1] : F.j_tiles, &tfirst, &tlast);
     for (uint32_t tile = tfirst; tile < tlast; ++tile) {
         uint32_t fidx;
         const FieldDesc fd = field_of_tile<false>(F, tile, &fidx);
@@ -577,8 +608,8 @@ __global__ __launch_bounds__(kBlock) void k_chase(Fields F, uint32_t* U, uint32_
                 pu[i] = ok[i] ? U[fd.vbase + lv[i]] : kMark;
                 pd[i] = ok[i] ? D[fd.vbase + lv[i]] : kMark;
             } else {
-                pu[i] = ok[i] ? uint32_t(fd.desc[lv[i]]) + fd.vbase : 0u;
-                pd[i] = ok[i] ? uint32_t(fd.asc[lv[i]]) + fd.vbase : 0u;
+                pu[i] = ok[i] ? uint32_t(gmem(fd.desc)[lv[i]]) + fd.vbase : 0u;
+                pd[i] = ok[i] ? uint32_t(gmem(fd.asc)[lv[i]]) + fd.vbase : 0u;
             }
         }
         if (CHASE) {
@@ -609,11 +640,11 @@ __global__ __launch_bounds__(kBlock) void k_chase(Fields F, uint32_t* U, uint32_
                 pu[i] &= ~kMark;
                 pd[i] &= ~kMark;
                 if (ok[i]) {
-                    fd.desc[lv[i]] = int32_t(pu[i] - fd.vbase);
-                    fd.asc[lv[i]] = int32_t(pd[i] - fd.vbase);
+                    gmem(fd.desc)[lv[i]] = int32_t(pu[i] - fd.vbase);
+                    gmem(fd.asc)[lv[i]] = int32_t(pd[i] - fd.vbase);
                 }
             }
-            if (pending && fd.info) fd.info[0] = -7;  // PLMSS_E_NOCONV
+            if (pending && fd.info) gmem(fd.info)[0] = -7;  // PLMSS_E_NOCONV
         }
         __syncthreads();
         // insert every vertex's pair; slot[i] = its hash slot
@@ -671,7 +702,7 @@ __global__ __launch_bounds__(kBlock) void k_chase(Fields F, uint32_t* U, uint32_
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < kJPer; ++i)
-            if (ok[i]) fd.ms[lv[i]] = int32_t(uint32_t(region) + dense[slot[i]]);
+            if (ok[i]) gmem(fd.ms)[lv[i]] = int32_t(uint32_t(region) + dense[slot[i]]);
         (void)fidx;
     }
 }
@@ -791,7 +822,7 @@ template <class T>
 __global__ __launch_bounds__(kBlock) void k_ms_final(Fields F, const uint32_t* off,
                                                      const uint32_t* rank_of, const uint32_t* fbase) {
     uint32_t tfirst, tlast;
-    block_tiles(F.dev_tiles ? F.dev_tiles[1] : F.j_tiles, &tfirst, &tlast);
+    block_tiles(F.dev_tiles ? gmem(F.dev_tiles)[1] : F.j_tiles, &tfirst, &tlast);
     for (uint32_t tile = tfirst; tile < tlast; ++tile) {
         uint32_t fidx;
         const FieldDesc fd = field_of_tile<false>(F, tile, &fidx);
@@ -805,11 +836,11 @@ __global__ __launch_bounds__(kBlock) void k_ms_final(Fields F, const uint32_t* o
             jtile_xyz<T>(fd, lt, threadIdx.x + i * kBlock, &x, &y, &z);
             ok[i] = x < fd.nx && y < fd.ny && z < fd.nz;
             lv[i] = (uint32_t(z) * uint32_t(fd.ny) + uint32_t(y)) * uint32_t(fd.nx) + uint32_t(x);
-            sl[i] = ok[i] ? uint32_t(fd.ms[lv[i]]) : 0u;
+            sl[i] = ok[i] ? uint32_t(gmem(fd.ms)[lv[i]]) : 0u;
         }
 #pragma unroll
         for (int i = 0; i < kJPer; ++i)
-            if (ok[i]) fd.ms[lv[i]] = int32_t(rank_of[off[sl[i] / kJV] + sl[i] % kJV] - base);
+            if (ok[i]) gmem(fd.ms)[lv[i]] = int32_t(rank_of[off[sl[i] / kJV] + sl[i] % kJV] - base);
     }
 }
 
@@ -821,7 +852,7 @@ __global__ __launch_bounds__(kBlock) void k_field_base(Fields F, const uint64_t*
                                                        int bn, uint32_t* fbase) {
     const uint32_t nf = fields_count(F), count = *count_ptr;
     for (uint32_t f = threadIdx.x; f < nf; f += kBlock) {
-        const FieldDesc fd = F.table ? F.table[f] : F.one;
+        const FieldDesc fd = field_desc(F, f);
         const uint64_t target = uint64_t(fd.vbase) << bn;
         uint32_t lo = 0, hi = count;
         while (lo < hi) {
@@ -835,7 +866,7 @@ __global__ __launch_bounds__(kBlock) void k_field_base(Fields F, const uint64_t*
     }
     __syncthreads();
     for (uint32_t f = threadIdx.x; f < nf; f += kBlock) {
-        const FieldDesc fd = F.table ? F.table[f] : F.one;
+        const FieldDesc fd = field_desc(F, f);
         const uint32_t next = f + 1 < nf ? fbase[f + 1] : *k_total;
         if (fd.info) fd.info[3] = int32_t(next - fbase[f]);
     }
@@ -845,7 +876,7 @@ __global__ __launch_bounds__(kBlock) void k_field_base(Fields F, const uint64_t*
 __global__ __launch_bounds__(kBlock) void k_init_fields(Fields F) {
     const uint32_t nf = fields_count(F);
     for (uint32_t f = blockIdx.x * kBlock + threadIdx.x; f < nf; f += gridDim.x * kBlock) {
-        const FieldDesc fd = F.table ? F.table[f] : F.one;
+        const FieldDesc fd = field_desc(F, f);
         if (fd.info) {
             fd.info[0] = 0;
             fd.info[1] = 0;

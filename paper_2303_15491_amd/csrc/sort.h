@@ -60,6 +60,40 @@ struct ArraySrc {
     __device__ __forceinline__ bool nan(uint32_t) const { return false; }
 };
 
+// 32-bit keys and their ids packed in one word, key in the high half: one
+// load and one store per item, and one output stream per digit.
+struct PackedSrc {
+    using key_t = uint32_t;
+    const uint64_t* kv;
+    __device__ __forceinline__ uint32_t key(uint32_t i) const { return uint32_t(kv[i] >> 32); }
+    __device__ __forceinline__ uint32_t val(uint32_t i) const { return uint32_t(kv[i]); }
+    __device__ __forceinline__ bool nan(uint32_t) const { return false; }
+};
+
+struct PackedDst {
+    uint64_t* kv;
+    __device__ __forceinline__ void put(uint32_t pos, uint32_t k, uint32_t v) const {
+        kv[pos] = (uint64_t(k) << 32) | v;
+    }
+};
+
+// One item of a source: key and value from a single read of its storage.
+template <typename T, typename K>
+__device__ __forceinline__ void load_item(const FieldSrc<T, K>& s, uint32_t i, K& k, uint32_t& v) {
+    k = s.key(i);
+    v = i;
+}
+template <typename K>
+__device__ __forceinline__ void load_item(const ArraySrc<K>& s, uint32_t i, K& k, uint32_t& v) {
+    k = s.keys[i];
+    v = s.vals[i];
+}
+__device__ __forceinline__ void load_item(const PackedSrc& s, uint32_t i, uint32_t& k, uint32_t& v) {
+    const uint64_t x = s.kv[i];
+    k = uint32_t(x >> 32);
+    v = uint32_t(x);
+}
+
 // ---- destinations ----------------------------------------------------------------
 
 template <typename K>
@@ -112,16 +146,24 @@ __device__ __forceinline__ int top_lane(uint64_t m) { return 63 - __clzll(static
 
 // ---- kernels -----------------------------------------------------------------------
 
-template <class Src, bool CHECK_NAN>
+// IDS: also counts the values (vertex ids) per id range, id >> id_shift, into
+// ihist (same layout), for the last pass of the order field.
+template <class Src, bool CHECK_NAN, bool IDS = false>
 __global__ __launch_bounds__(kBlock) void k_radix_hist(Src src, const uint32_t* count_ptr,
                                                        uint32_t n, int shift, uint32_t* hist,
-                                                       int32_t* info) {
+                                                       int32_t* info, int id_shift = 0,
+                                                       uint32_t* ihist = nullptr) {
     using K = typename Src::key_t;
     __shared__ uint32_t h[kWavesPerBlock][kRadix];
+    __shared__ uint32_t hi_ids[IDS ? kWavesPerBlock : 1][kRadix];
     __shared__ int nan_seen;
     const int t = threadIdx.x, w = wave_id();
 #pragma unroll
     for (int i = 0; i < kWavesPerBlock; ++i) h[i][t] = 0;
+    if (IDS) {
+#pragma unroll
+        for (int i = 0; i < kWavesPerBlock; ++i) hi_ids[IDS ? i : 0][t] = 0;
+    }
     if (t == 0) nan_seen = 0;
     __syncthreads();
     uint32_t lo, hi;
@@ -129,16 +171,29 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(Src src, const uint32_t* 
     bool bad = false;
     for (uint32_t tile = lo; tile < hi; tile += kTile) {
         K key[kItems];
+        uint32_t val[kItems];
 #pragma unroll
         for (int i = 0; i < kItems; ++i) {
             const uint32_t idx = tile + uint32_t(i) * kBlock + t;
-            key[i] = idx < hi ? src.key(idx) : K(0);
+            if (IDS) {
+                if (idx < hi) {
+                    load_item(src, idx, key[i], val[i]);
+                } else {
+                    key[i] = K(0);
+                    val[i] = 0u;
+                }
+            } else {
+                key[i] = idx < hi ? src.key(idx) : K(0);
+            }
             if (CHECK_NAN && idx < hi) bad |= src.nan(idx);
         }
 #pragma unroll
         for (int i = 0; i < kItems; ++i) {
             const uint32_t idx = tile + uint32_t(i) * kBlock + t;
-            if (idx < hi) atomicAdd(&h[w][digit_of(key[i], shift)], 1u);
+            if (idx < hi) {
+                atomicAdd(&h[w][digit_of(key[i], shift)], 1u);
+                if (IDS) atomicAdd(&hi_ids[IDS ? w : 0][val[i] >> id_shift], 1u);
+            }
         }
     }
     if (CHECK_NAN && bad) nan_seen = 1;
@@ -147,6 +202,12 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(Src src, const uint32_t* 
 #pragma unroll
     for (int i = 0; i < kWavesPerBlock; ++i) s += h[i][t];
     hist[size_t(t) * gridDim.x + blockIdx.x] = s;
+    if (IDS) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int i = 0; i < kWavesPerBlock; ++i) c += hi_ids[IDS ? i : 0][t];
+        ihist[size_t(t) * gridDim.x + blockIdx.x] = c;
+    }
     if (CHECK_NAN && t == 0 && nan_seen && info) info[0] = -4;  // PLMSS_E_NAN
 }
 
@@ -277,6 +338,219 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(Src src, Dst dst,
         __syncthreads();
         sm.run[t] += sm.tcount[t];
     }
+}
+
+// Last pass of the order field without a scattered write over the whole
+// order array: each key's sorted position comes from the same stable rank by
+// the top digit as in k_radix_scatter, and the pair (id, position) is then
+// written to one of 256 id ranges (id >> id_shift), so that k_invert_ranges
+// writes order[] one range at a time.  ihist/itotal: the per-worker id-range
+// counts and their totals (k_radix_hist with IDS, then k_radix_digit_scan).
+template <class Src>
+__global__ __launch_bounds__(kBlock) void k_rank_partition(Src src, uint32_t n, int shift,
+                                                           const uint32_t* hist, const uint32_t* dtotal,
+                                                           const uint32_t* ihist, const uint32_t* itotal,
+                                                           int id_shift, uint64_t* out) {
+    using K = typename Src::key_t;
+    __shared__ uint32_t wcnt[kWavesPerBlock][kRadix];
+    __shared__ uint32_t run[kRadix], tstart[kRadix], tcount[kRadix];
+    __shared__ uint32_t irun[kRadix], istart[kRadix], icount[kRadix], ifill[kRadix];
+    __shared__ uint64_t stage[kTile];
+    __shared__ uint32_t tmp[kWavesPerBlock];
+    const int t = threadIdx.x, w = wave_id(), lane = lane_id();
+    uint32_t tot;
+    run[t] = block_exclusive_scan(dtotal[t], tmp, &tot) + hist[size_t(t) * gridDim.x + blockIdx.x];
+    irun[t] = block_exclusive_scan(itotal[t], tmp, &tot) + ihist[size_t(t) * gridDim.x + blockIdx.x];
+    uint32_t lo, hi;
+    worker_range(n, blockIdx.x, gridDim.x, kTile, &lo, &hi);
+    const uint64_t lt = lanemask_lt();
+    for (uint32_t tile = lo; tile < hi; tile += kTile) {
+        const uint32_t tsize = min(uint32_t(kTile), hi - tile);
+#pragma unroll
+        for (int i = 0; i < kWavesPerBlock; ++i) wcnt[i][t] = 0;
+        icount[t] = 0;
+        ifill[t] = 0;
+        K key[kItems];
+        uint32_t val[kItems];
+        const uint32_t wbase = tile + uint32_t(w) * kWave * kItems + lane;
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            const uint32_t idx = wbase + uint32_t(i) * kWave;
+            if (idx < hi) {
+                load_item(src, idx, key[i], val[i]);
+            } else {
+                key[i] = K(0);
+                val[i] = 0u;
+            }
+        }
+        __syncthreads();
+        uint32_t local[kItems], prior[kItems];
+        int leader[kItems];
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            const uint32_t idx = wbase + uint32_t(i) * kWave;
+            const bool valid = idx < hi;
+            const uint32_t d = digit_of(key[i], shift);
+            const uint64_t peers = match_digit(d, valid);
+            leader[i] = peers ? top_lane(peers) : lane;
+            local[i] = uint32_t(__popcll(peers & lt));
+            prior[i] = 0;
+            if (valid && leader[i] == lane) prior[i] = atomicAdd(&wcnt[w][d], uint32_t(__popcll(peers)));
+            if (valid) atomicAdd(&icount[val[i] >> id_shift], 1u);
+        }
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) local[i] += uint32_t(__shfl(int(prior[i]), leader[i]));
+        __syncthreads();
+        {
+            uint32_t c[kWavesPerBlock], sum = 0;
+#pragma unroll
+            for (int i = 0; i < kWavesPerBlock; ++i) {
+                c[i] = wcnt[i][t];
+                sum += c[i];
+            }
+            uint32_t ttot;
+            uint32_t acc = block_exclusive_scan(sum, tmp, &ttot);
+            tstart[t] = acc;
+            tcount[t] = sum;
+#pragma unroll
+            for (int i = 0; i < kWavesPerBlock; ++i) {
+                wcnt[i][t] = acc;
+                acc += c[i];
+            }
+            istart[t] = block_exclusive_scan(icount[t], tmp, &ttot);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            const uint32_t idx = wbase + uint32_t(i) * kWave;
+            if (idx < hi) {
+                const uint32_t d = digit_of(key[i], shift);
+                const uint32_t pos = run[d] + (wcnt[w][d] + local[i] - tstart[d]);
+                const uint32_t r = val[i] >> id_shift;
+                const uint32_t slot = istart[r] + atomicAdd(&ifill[r], 1u);
+                stage[slot] = (uint64_t(val[i]) << 32) | pos;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            const uint32_t j = uint32_t(i) * kBlock + t;
+            if (j < tsize) {
+                const uint64_t x = stage[j];
+                const uint32_t r = uint32_t(x >> 32) >> id_shift;
+                out[irun[r] + (j - istart[r])] = x;
+            }
+        }
+        __syncthreads();
+        run[t] += tcount[t];
+        irun[t] += icount[t];
+    }
+}
+
+// The inversion order[id] = position by id chunks of kChunk ids, each
+// inverted inside one block's LDS so that order[] is written in whole
+// coalesced rows.  The pairs reach their chunk in two regroupings with long
+// write runs: k_rank_partition groups them by range (id >> range_shift: at
+// most 256 ranges of 1 to 256 chunks), k_chunk_partition by chunk inside the
+// ranges.  A chunk c holds exactly min(kChunk, n - c*kChunk) pairs (the ids
+// are a permutation), so its pairs go to [c*kChunk, c*kChunk + that count).
+constexpr int kChunkBits = 15;
+constexpr uint32_t kChunk = 1u << kChunkBits;  // 128 KB of order per block
+constexpr int kMaxRel = 512;                   // chunks a tile can touch: two ranges of <= 256
+constexpr int kInvertBlock = 1024;
+
+__device__ __forceinline__ uint32_t chunk_count(uint32_t c, uint32_t n) {
+    const uint32_t base = c << kChunkBits;
+    return min(kChunk, n - base);
+}
+
+// chunk_fill: u32 per chunk, zero on entry.  Grid: one block per kTile pairs.
+__global__ __launch_bounds__(kBlock) void k_chunk_partition(const uint64_t* parts, uint32_t n, int range_shift,
+                                                            uint32_t* chunk_fill, uint64_t* out) {
+    __shared__ uint32_t cnt[kMaxRel], start[kMaxRel], base[kMaxRel], fill[kMaxRel];
+    __shared__ uint64_t stage[kTile];
+    __shared__ uint32_t tmp[kWavesPerBlock];
+    __shared__ uint32_t s_first;
+    const int t = threadIdx.x;
+    const uint32_t lo = blockIdx.x * uint32_t(kTile);
+    const uint32_t hi = min(n, lo + uint32_t(kTile));
+    for (int i = t; i < kMaxRel; i += kBlock) {
+        cnt[i] = 0;
+        fill[i] = 0;
+    }
+    // first chunk of the range the tile starts in (pairs are grouped by range)
+    if (t == 0) s_first = ((uint32_t(parts[lo] >> 32) >> range_shift) << (range_shift - kChunkBits));
+    __syncthreads();
+    const uint32_t first = s_first;
+    uint64_t x[kItems];
+    uint32_t rel[kItems];
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        const uint32_t j = lo + uint32_t(i) * kBlock + t;
+        x[i] = j < hi ? parts[j] : 0ull;
+        rel[i] = j < hi ? (uint32_t(x[i] >> 32) >> kChunkBits) - first : uint32_t(kMaxRel);
+        if (rel[i] < uint32_t(kMaxRel)) atomicAdd(&cnt[rel[i]], 1u);
+    }
+    __syncthreads();
+    constexpr int kPer = kMaxRel / kBlock;
+    uint32_t c[kPer], sum = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        c[k] = cnt[t * kPer + k];
+        sum += c[k];
+    }
+    uint32_t tot;
+    uint32_t e = block_exclusive_scan(sum, tmp, &tot);
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        start[t * kPer + k] = e;
+        base[t * kPer + k] = c[k] ? atomicAdd(&chunk_fill[first + uint32_t(t * kPer + k)], c[k]) : 0u;
+        e += c[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kItems; ++i)
+        if (rel[i] < uint32_t(kMaxRel)) stage[start[rel[i]] + atomicAdd(&fill[rel[i]], 1u)] = x[i];
+    __syncthreads();
+    const uint32_t tsize = hi > lo ? hi - lo : 0u;
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        const uint32_t j = uint32_t(i) * kBlock + t;
+        if (j < tsize) {
+            const uint64_t y = stage[j];
+            const uint32_t ch = uint32_t(y >> 32) >> kChunkBits;
+            const uint32_t r = ch - first;
+            const uint32_t slot = base[r] + (j - start[r]);
+            if (slot < chunk_count(ch, n)) out[(size_t(ch) << kChunkBits) + slot] = y;
+        }
+    }
+}
+
+// One block per chunk: order[c*kChunk + i] for the chunk's pairs, through LDS.
+__global__ __launch_bounds__(kInvertBlock) void k_invert_chunks(const uint64_t* parts, uint32_t n, int32_t* order) {
+    __shared__ uint32_t buf[kChunk];
+    const uint32_t base = blockIdx.x << kChunkBits;
+    const uint32_t cnt = chunk_count(blockIdx.x, n);
+    constexpr int kBatch = 8;
+    for (uint32_t j0 = 0; j0 < cnt; j0 += uint32_t(kInvertBlock * kBatch)) {
+        uint64_t x[kBatch];
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            const uint32_t j = j0 + uint32_t(k * kInvertBlock) + threadIdx.x;
+            x[k] = j < cnt ? parts[base + j] : ~0ull;
+        }
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            const uint32_t r = uint32_t(x[k] >> 32) - base;
+            if (x[k] != ~0ull && r < cnt) buf[r] = uint32_t(x[k]);
+        }
+    }
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < cnt; j += kInvertBlock) order[base + j] = int32_t(buf[j]);
+}
+
+__global__ void k_zero_u32(uint32_t* p, uint32_t n) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
 
 // order[ids[i]] = i for the ids in [lo, hi): the inversion of the sorted ids,

@@ -107,9 +107,12 @@ def test_tuning_knobs_validate_ranges():
         assert lib.plmss_tune_get(plmss.KNOBS["sort_workers"]) == saved["sort_workers"]
         assert lib.plmss_tune_set(plmss.KNOBS["scan_depth"], 24) == plmss.E_ARG
         assert lib.plmss_tune_set(plmss.KNOBS["scan_depth"], 64) == plmss.E_ARG
-        plmss.tune_set(order_workers=0, order_windows=0, sort_workers=512, persist_blocks=4096, scan_depth=8)
-        assert plmss.tune_get() == {"order_workers": 0, "order_windows": 0, "sort_workers": 512,
-                                    "persist_blocks": 4096, "scan_depth": 8}
+        assert lib.plmss_tune_set(plmss.KNOBS["order_packed"], 2) == plmss.E_ARG
+        assert lib.plmss_tune_set(plmss.KNOBS["order_invert"], 65) == plmss.E_ARG
+        plmss.tune_set(order_workers=0, order_invert=0, sort_workers=512, persist_blocks=4096, scan_depth=8,
+                       order_packed=0)
+        assert plmss.tune_get() == {"order_workers": 0, "order_invert": 0, "sort_workers": 512,
+                                    "persist_blocks": 4096, "scan_depth": 8, "order_packed": 0}
         with pytest.raises(plmss.PlmssError):
             plmss.tune_set(order_workers=10)
         with pytest.raises(KeyError):

@@ -84,8 +84,12 @@ def test_ragged_tiles_both_paths(torch, shape):
 
 
 @pytest.mark.parametrize("knobs", [
-    {"scan_depth": 8}, {"scan_depth": 32}, {"order_windows": 0}, {"order_windows": 3, "order_workers": 64},
-    {"order_windows": 64, "order_workers": 4096}, {"sort_workers": 64}, {"sort_workers": 4096},
+    {"scan_depth": 8}, {"scan_depth": 32}, {"order_invert": 0}, {"order_invert": 5},
+    {"order_invert": 1, "order_workers": 0}, {"order_invert": 1, "order_workers": 64},
+    {"order_packed": 0, "order_invert": 1}, {"order_packed": 0, "order_invert": 0},
+    {"order_packed": 0, "order_invert": 3, "order_workers": 64},
+    {"order_packed": 0, "order_invert": 64, "order_workers": 0},
+    {"sort_workers": 64}, {"sort_workers": 4096},
 ])
 def test_launch_shapes_keep_results(torch, knobs):
     """Every launch-shape knob setting gives the oracle's labels (tile depths
