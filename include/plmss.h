@@ -238,8 +238,11 @@ const char* plmss_kernel_name(int32_t kind);
  *                              2..64 = the last pass writes the sorted ids and
  *                              w launches invert them, each for 1/w of the id
  *                              range.
- *   PLMSS_TUNE_ORDER_PACKED    1 (default) = 32-bit keys travel packed with
- *                              their ids in one 64-bit word; 0 = two arrays.
+ *   PLMSS_TUNE_ORDER_PACKED    1 = 32-bit keys travel packed with their ids
+ *                              in one 64-bit word; 0 (default) = two arrays.
+ *   PLMSS_TUNE_SCAN_ROUNDS     in-tile path-compression sweeps of the
+ *                              neighbour scan (1..8, default 3); what they
+ *                              leave unfinished the cross-tile chase follows.
  *   PLMSS_TUNE_SORT_WORKERS    blocks of device-sized sorts and scans (the MS
  *                              pair sort): 64..4096, default 1024.
  *   PLMSS_TUNE_PERSIST_BLOCKS  grid of a plan's persistent launches:
@@ -260,7 +263,8 @@ const char* plmss_kernel_name(int32_t kind);
 #define PLMSS_TUNE_PERSIST_BLOCKS 3
 #define PLMSS_TUNE_SCAN_DEPTH 4
 #define PLMSS_TUNE_ORDER_PACKED 5
-#define PLMSS_TUNE_KNOBS 6
+#define PLMSS_TUNE_SCAN_ROUNDS 6
+#define PLMSS_TUNE_KNOBS 7
 int32_t plmss_tune_set(int32_t knob, int64_t value);
 int64_t plmss_tune_get(int32_t knob);
 

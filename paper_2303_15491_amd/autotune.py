@@ -2,9 +2,9 @@
 
 The library exposes a few knobs (``plmss_tune_set``): the blocks of each
 order-field radix pass, how the order field is inverted, whether 32-bit keys
-travel packed with their ids, the grid of the
-device-sized pair sort, the z-depth of the 3-D neighbour-scan tiles, and the
-grid of a plan's persistent launches.  None of them changes a result; they
+travel packed with their ids, the grid of the device-sized pair sort, the
+z-depth of the 3-D neighbour-scan tiles and their in-tile compression sweeps,
+and the grid of a plan's persistent launches.  None of them changes a result; they
 trade occupancy, tile-local path compression and write locality against each
 other, and the best values depend on the field's size and shape.
 
@@ -29,15 +29,16 @@ from . import KNOBS, Plan, PlmssError, batch_needs, segment, tune_get, tune_set
 SPACE = {
     "order_workers": [8192, 4096, 16384, 0],
     "order_invert": [1, 0, 2, 4],
-    "order_packed": [1, 0],
+    "order_packed": [0, 1],
+    "scan_rounds": [3, 2, 4],
     "sort_workers": [256, 512, 1024, 2048, 4096],
     "scan_depth": [8, 16, 32],
     "persist_blocks": [512, 1024, 2048, 4096, 8192],
 }
 
-SEGMENT_KNOBS = ("scan_depth", "sort_workers")
+SEGMENT_KNOBS = ("scan_depth", "scan_rounds", "sort_workers")
 ORDER_KNOBS = ("order_invert", "order_packed", "order_workers")
-BATCH_KNOBS = ("persist_blocks", "scan_depth", "sort_workers")
+BATCH_KNOBS = ("persist_blocks", "scan_depth", "scan_rounds", "sort_workers")
 
 _lock = threading.Lock()
 

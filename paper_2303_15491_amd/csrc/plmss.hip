@@ -31,15 +31,18 @@ constexpr KnobRange kKnobs[PLMSS_TUNE_KNOBS] = {
     {64, kMaxWorkers, kWorkers, false, false},  // SORT_WORKERS
     {64, 16384, 2048, false, false},           // PERSIST_BLOCKS
     {8, 32, 16, false, true},                  // SCAN_DEPTH: 8, 16 or 32 planes
-    {1, 1, 1, true, false},                    // ORDER_PACKED: 32-bit keys packed with ids
+    {1, 1, 0, true, false},                    // ORDER_PACKED: 32-bit keys packed with ids
+    {1, 8, kResolveRounds, false, false},      // SCAN_ROUNDS: in-tile jumping sweeps
 };
 std::atomic<int64_t> g_knob[PLMSS_TUNE_KNOBS] = {kKnobs[0].def, kKnobs[1].def, kKnobs[2].def,
-                                                 kKnobs[3].def, kKnobs[4].def, kKnobs[5].def};
+                                                 kKnobs[3].def, kKnobs[4].def, kKnobs[5].def,
+                                                 kKnobs[6].def};
 
 int64_t knob(int k) { return g_knob[k].load(std::memory_order_relaxed); }
 unsigned sort_workers() { return unsigned(knob(PLMSS_TUNE_SORT_WORKERS)); }
 unsigned persist_blocks() { return unsigned(knob(PLMSS_TUNE_PERSIST_BLOCKS)); }
 int scan_depth() { return int(knob(PLMSS_TUNE_SCAN_DEPTH)); }
+int scan_rounds() { return int(knob(PLMSS_TUNE_SCAN_ROUNDS)); }
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -398,15 +401,16 @@ template <bool RESOLVE, class Src>
 void launch_steepest_cls(int c, int zc, const Fields& F, unsigned grid, uint32_t* up, uint32_t* dn,
                          hipStream_t s) {
     if (grid == 0) return;
+    const int rounds = scan_rounds();
     launch(PLMSS_KERNEL_STEEPEST, s, [&] {
         if (c != 0)
-            k_steepest<Src, 16, 1, RESOLVE><<<grid, kBlock, 0, s>>>(F, up, dn);
+            k_steepest<Src, 16, 1, RESOLVE><<<grid, kBlock, 0, s>>>(F, up, dn, rounds);
         else if (zc == 8)
-            k_steepest<Src, 8, 8, RESOLVE><<<grid, kBlock, 0, s>>>(F, up, dn);
+            k_steepest<Src, 8, 8, RESOLVE><<<grid, kBlock, 0, s>>>(F, up, dn, rounds);
         else if (zc == 32)
-            k_steepest<Src, 8, 32, RESOLVE><<<grid, kBlock, 0, s>>>(F, up, dn);
+            k_steepest<Src, 8, 32, RESOLVE><<<grid, kBlock, 0, s>>>(F, up, dn, rounds);
         else
-            k_steepest<Src, 8, 16, RESOLVE><<<grid, kBlock, 0, s>>>(F, up, dn);
+            k_steepest<Src, 8, 16, RESOLVE><<<grid, kBlock, 0, s>>>(F, up, dn, rounds);
     });
 }
 

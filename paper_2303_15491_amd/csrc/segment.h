@@ -195,7 +195,18 @@ __device__ __forceinline__ void steepest_codes(const typename Src::key_t (*pl)[P
 constexpr uint32_t kMark = 0x80000000u;     // "this label is an extremum" in a resolved pointer
 constexpr uint32_t kMaxHops = 1u << 24;     // iteration cap of the pointer-chasing loops
 constexpr uint32_t kExit = 0x8000u;         // local pointer: the target lies outside the tile
-constexpr int kResolveRounds = 3;           // in-tile jumping sweeps
+constexpr int kResolveRounds = 3;           // in-tile jumping sweeps (default)
+
+// In-tile move of neighbour code c in a kTX x ty x zc tile: bits 0-15 the
+// change of the local index (two's complement), bits 16-21 the tile sides the
+// move crosses when taken from a vertex on that side (x-, x+, y-, y+, z-, z+).
+__host__ __device__ constexpr uint32_t local_move(int c, int ty) {
+    const int d = c - 7, m = d < 0 ? -d : d;
+    const int dx = m & 1, dy = (m >> 1) & 1, dz = (m >> 2) & 1;
+    const int delta = dx + dy * kTX + dz * kTX * ty;
+    const uint32_t side = d < 0 ? uint32_t(dx | (dy << 2) | (dz << 4)) : uint32_t((dx << 1) | (dy << 3) | (dz << 5));
+    return (side << 16) | (uint32_t(d < 0 ? -delta : delta) & 0xffffu);
+}
 
 // Steepest neighbours of every vertex.
 //
@@ -231,7 +242,7 @@ struct SquarePlanes {
 };
 
 template <class Src, int TY, int ZC, bool RESOLVE>
-__global__ __launch_bounds__(kBlock) void k_steepest(Fields F, uint32_t* up, uint32_t* dn) {
+__global__ __launch_bounds__(kBlock) void k_steepest(Fields F, uint32_t* up, uint32_t* dn, int rounds) {
     using K = typename Src::key_t;
     constexpr bool kSquares = sizeof(K) == 4;
     constexpr int PX = kTX + 2, PY = TY + 2, RPW = TY / kWavesPerBlock;
@@ -248,9 +259,13 @@ __global__ __launch_bounds__(kBlock) void k_steepest(Fields F, uint32_t* up, uin
     __shared__ SquarePlanes<K, kSquares ? TY : 0> sq;
     __shared__ uint32_t lp[TV];  // local pointers: up in the low half, dn in the high half
     __shared__ int32_t off_tab[16];  // vertex-id offset of each neighbour code
+    __shared__ uint32_t loc_tab[16];  // in-tile move of each neighbour code
     __shared__ uint32_t cnt_min, cnt_max;
     __shared__ int nan_seen;
     const int t = threadIdx.x, w = wave_id(), lane = lane_id();
+    if (t < 16) loc_tab[t] = t < 15 ? local_move(t, TY) : 0u;
+    // the x sides of this thread's column (the y and z sides are uniform)
+    const uint32_t xside = (lane == 0 ? 1u : 0u) | (lane == kTX - 1 ? 2u : 0u);
     uint32_t tfirst, tlast;
     block_tiles(F.dev_tiles ? gmem(F.dev_tiles)[0] : F.s_tiles, &tfirst, &tlast);
     for (uint32_t tile = tfirst; tile < tlast; ++tile) {
@@ -415,17 +430,17 @@ __global__ __launch_bounds__(kBlock) void k_steepest(Fields F, uint32_t* up, uin
                 }
             } else {
                 const int li = (lz * TY + ly) * kTX + lane;
+                // the tile sides this vertex lies on; a move across one of
+                // them leaves the tile and is kept as an exit mark with its code
+                const uint32_t side = xside | (ly == 0 ? 4u : 0u) | (ly == TY - 1 ? 8u : 0u) |
+                                      (lz == 0 ? 16u : 0u) | (lz == ZC - 1 ? 32u : 0u);
                 auto local = [&](int c) -> uint32_t {
-                    const int d = c - kSelf, m = d < 0 ? -d : d;
-                    const int dx = (m & 1), dy = (m >> 1) & 1, dz = (m >> 2) & 1;
-                    const int ax = d < 0 ? lane - dx : lane + dx, ay = d < 0 ? ly - dy : ly + dy,
-                              az = d < 0 ? lz - dz : lz + dz;
-                    const bool in = uint32_t(ax) < uint32_t(kTX) && uint32_t(ay) < uint32_t(TY) &&
-                                    uint32_t(az) < uint32_t(ZC);
-                    return !inside ? uint32_t(li)  // padding: a harmless root
-                                   : in ? uint32_t((az * TY + ay) * kTX + ax) : (kExit | uint32_t(c));
+                    const uint32_t mv = loc_tab[c];
+                    return ((mv >> 16) & side) ? (kExit | uint32_t(c))
+                                               : uint32_t(li + int32_t(int16_t(uint16_t(mv & 0xffffu))));
                 };
-                lp[li] = local(cu) | (local(cd) << 16);
+                // padding (outside the grid) is a harmless root
+                lp[li] = inside ? (local(cu) | (local(cd) << 16)) : (uint32_t(li) | (uint32_t(li) << 16));
             }
         }
         const int tmp = pm;
@@ -438,39 +453,35 @@ __global__ __launch_bounds__(kBlock) void k_steepest(Fields F, uint32_t* up, uin
         // entries of this thread: (lz, row) pairs over the tile's planes; entry
         // e has local index li0 + (e / RPW) * TY * kTX + (e % RPW) * kTX
         constexpr int kMine = ZC * RPW;
-        static_assert(kMine <= 64, "one mask bit per entry");
-        using Mask = typename std::conditional<(kMine > 32), uint64_t, uint32_t>::type;
         const int nz_t = z1 - z0;
         const int li0 = (w * RPW) * kTX + lane;
-        Mask todo = 0;
-#pragma unroll
-        for (int e = 0; e < kMine; ++e) {
-            const int lz = e / RPW, ly = w * RPW + e % RPW;
-            if (lz < nz_t && x < g.nx && y0 + ly < g.ny) todo |= Mask(1) << e;
-        }
-        // in-place rounds of p <- p[p]; an entry is finished once both of its
-        // pointers reach an exit vertex or a root.  The loop over entries is
-        // uniform; an entry no lane of the wave still needs is skipped.
+        // in-place rounds of p <- p[p] on both halves of an entry at once.  A
+        // half stays when it or its target is an exit mark, or when its target
+        // is a root (points to itself); otherwise it takes the target's
+        // pointer.  Planes past the field's last plane hold nothing of this
+        // tile and are skipped; every pointer written above stays in the
+        // planes that were written.
         auto step = [&](int e, bool& ch) {
-            const bool mine = (todo >> e) & Mask(1);
-            if (!__ballot(mine)) return;
+            if (e / RPW >= nz_t) return;
             const int li = li0 + (e / RPW) * (TY * kTX) + (e % RPW) * kTX;
             const uint32_t own = lp[li];
-            const uint32_t pu = own & 0xffffu, pd = own >> 16;
-            const uint32_t qu = lp[pu & (kExit - 1)] & 0xffffu, qd = lp[pd & (kExit - 1)] >> 16;
-            const bool su = ((pu | qu) & kExit) || qu == pu;  // cannot move
-            const bool sd = ((pd | qd) & kExit) || qd == pd;
-            const uint32_t nu = (mine && !su) ? qu : pu, nd = (mine && !sd) ? qd : pd;
-            // an entry has one owner, so rewriting an unchanged value is harmless
-            lp[li] = nu | (nd << 16);
-            ch |= (nu != pu) || (nd != pd);
-            todo &= (su && sd) ? ~(Mask(1) << e) : ~Mask(0);
+            const uint32_t qu = lp[own & (kExit - 1)], qd = lp[(own >> 16) & (kExit - 1)];
+            const uint32_t q = (qu & 0xffffu) | (qd & 0xffff0000u);
+            const uint32_t cross = own | q, diff = own ^ q;
+            const bool su = (cross & kExit) || (diff & 0xffffu) == 0u;
+            const bool sd = (cross & (kExit << 16)) || (diff >> 16) == 0u;
+            const uint32_t keep = (su ? 0x0000ffffu : 0u) | (sd ? 0xffff0000u : 0u);
+            const uint32_t nw = (own & keep) | (q & ~keep);
+            if (nw != own) {
+                lp[li] = nw;  // each entry has one owner
+                ch = true;
+            }
         };
         // sweeps alternate direction, so chains of either orientation compress
         // in one sweep when their entries happen to lie in sweep order.  A few
         // sweeps finish almost every tile chain; what is left is written as an
         // unfinished pointer, which the chase kernel follows.
-        for (int round = 0; round < kResolveRounds; ++round) {
+        for (int round = 0; round < rounds; ++round) {
             bool ch = false;
             if (round & 1) {
 #pragma unroll
