@@ -91,13 +91,12 @@ uint32_t j_tiles_of(const plmss_dims& d) {
 // ---- workspace ----------------------------------------------------------------------
 
 struct Work {
-    uint8_t* keys[2];    // u64[max(npad, regions*kJV)] each: sort keys (ping-pong).
-                         // keys[0] also holds the tile-compressed pointers U, D
-                         // (u32[npad] each) and keys[1] the per-tile pair lists
+    uint8_t* keys[2];    // u64[npad] each: sort keys (ping-pong).  keys[0] also
+                         // holds the tile-compressed pointers U, D (u32[npad]
+                         // each) and keys[1] the listed MS pairs (at most one
+                         // per vertex)
     uint32_t* vals[2];   // u32[npad] each: sort values
     uint32_t* rank_of;   // u32[npad]: MS id of each listed pair (dense index)
-    uint32_t* reg_cnt;   // u32[regions]: pairs listed per chase tile
-    uint32_t* reg_off;   // u32[regions]: their exclusive prefix
     uint32_t* hist;      // u32[kRadix * max(kMaxWorkers, ntiles)]
     uint32_t* dtotal;    // u32[kRadix]
     uint32_t* partial;   // u32[kMaxWorkers]
@@ -109,7 +108,7 @@ struct Work {
 };
 
 struct Sizes {
-    size_t keys, vals, rank, regions, hist, dtotal, partial, counters, sortaux, fbase, tables, total;
+    size_t keys, vals, rank, hist, dtotal, partial, counters, sortaux, fbase, tables, total;
     uint64_t npad;
 };
 
@@ -119,16 +118,14 @@ constexpr size_t kSortAux = kRadix + (size_t(1) << (31 - kChunkBits));
 
 uint64_t n_tiles(uint64_t n) { return (n + kTile - 1) / kTile; }
 
-// nv vertices, `regions` chase tiles; table_stride > 0 reserves batch tables
-// of that many entries per range (all fields + 3 classes).
-Sizes work_sizes(uint64_t nv, uint64_t regions, uint64_t nfields, uint64_t table_stride) {
+// nv vertices; table_stride > 0 reserves batch tables of that many entries per
+// range (all fields + 3 classes).
+Sizes work_sizes(uint64_t nv, uint64_t nfields, uint64_t table_stride) {
     Sizes s;
     s.npad = align_up(std::max<uint64_t>(nv, 1), kBlock);
-    const uint64_t rec = std::max<uint64_t>(s.npad, regions * kJV);
-    s.keys = align_up(8 * rec, 256);
+    s.keys = align_up(8 * s.npad, 256);
     s.vals = align_up(4 * s.npad, 256);
     s.rank = align_up(4 * s.npad, 256);
-    s.regions = align_up(4 * std::max<uint64_t>(regions, 1), 256);
     s.hist = align_up(size_t(4) * kRadix * std::max<uint64_t>(kMaxWorkers, n_tiles(nv)), 256);
     s.dtotal = align_up(4 * kRadix, 256);
     s.partial = align_up(4 * kMaxWorkers, 256);
@@ -136,7 +133,7 @@ Sizes work_sizes(uint64_t nv, uint64_t regions, uint64_t nfields, uint64_t table
     s.sortaux = align_up(4 * kSortAux, 256);
     s.fbase = align_up(4 * std::max<uint64_t>(nfields, 1), 256);
     s.tables = table_stride ? align_up(sizeof(FieldDesc) * 4 * table_stride, 256) : 0;
-    s.total = 2 * s.keys + 2 * s.vals + s.rank + 2 * s.regions + s.hist + s.dtotal + s.partial +
+    s.total = 2 * s.keys + 2 * s.vals + s.rank + s.hist + s.dtotal + s.partial +
               s.counters + s.sortaux + s.fbase + s.tables;
     return s;
 }
@@ -154,8 +151,6 @@ Work carve(void* ws, const Sizes& s) {
     w.vals[0] = reinterpret_cast<uint32_t*>(take(s.vals));
     w.vals[1] = reinterpret_cast<uint32_t*>(take(s.vals));
     w.rank_of = reinterpret_cast<uint32_t*>(take(s.rank));
-    w.reg_cnt = reinterpret_cast<uint32_t*>(take(s.regions));
-    w.reg_off = reinterpret_cast<uint32_t*>(take(s.regions));
     w.hist = reinterpret_cast<uint32_t*>(take(s.hist));
     w.dtotal = reinterpret_cast<uint32_t*>(take(s.dtotal));
     w.partial = reinterpret_cast<uint32_t*>(take(s.partial));
@@ -354,29 +349,24 @@ void order_any(const void* field, int32_t dtype, uint32_t n, int32_t* order, con
         sort_order<double, uint64_t>(static_cast<const double*>(field), n, order, w, info, s);
 }
 
-// Sorts the listed (asc, desc) pair keys in keys[0]/vals[0] (count in
-// counters[0], known only on the device); returns the buffer holding the result.
-int sort_pairs(int bits, const Work& w, hipStream_t s) {
+// Sorts the listed (asc, desc) pair keys (keys[1], record indices in vals[0];
+// the count in counters[0], known only on the device).
+struct PairList {
+    const uint64_t* keys;
+    const uint32_t* vals;
+};
+
+PairList sort_pairs(int bits, const Work& w, hipStream_t s) {
     const int passes = (bits + kRadixBits - 1) / kRadixBits;
-    uint64_t* keys[2] = {reinterpret_cast<uint64_t*>(w.keys[0]),
-                         reinterpret_cast<uint64_t*>(w.keys[1])};
+    uint64_t* keys[2] = {reinterpret_cast<uint64_t*>(w.keys[1]), reinterpret_cast<uint64_t*>(w.keys[0])};
+    uint32_t* vals[2] = {w.vals[0], w.vals[1]};
     int cur = 0;
     for (int p = 0; p < passes; ++p) {
-        radix_pass(ArraySrc<uint64_t>{keys[cur], w.vals[cur]},
-                   ArrayDst<uint64_t>{keys[cur ^ 1], w.vals[cur ^ 1]}, w.counters, 0, sort_workers(),
-                   kRadixBits * p, false, w, nullptr, s);
+        radix_pass(ArraySrc<uint64_t>{keys[cur], vals[cur]}, ArrayDst<uint64_t>{keys[cur ^ 1], vals[cur ^ 1]},
+                   w.counters, 0, sort_workers(), kRadixBits * p, false, w, nullptr, s);
         cur ^= 1;
     }
-    return cur;
-}
-
-// Exclusive prefix of in[0..m) into out; m from m_dev when given.
-void prefix_sum(const uint32_t* in, const uint32_t* m_dev, uint32_t m, uint32_t* out,
-                uint32_t* total, const Work& w, hipStream_t s) {
-    const unsigned nw = sort_workers();
-    launch(PLMSS_KERNEL_PREFIX, s, [&] { k_sum_reduce<<<nw, kBlock, 0, s>>>(in, m_dev, m, w.partial); });
-    launch(PLMSS_KERNEL_PREFIX, s, [&] { k_scan_partials<<<1, kBlock, 0, s>>>(w.partial, int(nw), total); });
-    launch(PLMSS_KERNEL_PREFIX, s, [&] { k_scan_apply<<<nw, kBlock, 0, s>>>(in, m_dev, m, w.partial, out); });
+    return {keys[cur], vals[cur]};
 }
 
 // ---- one launch over a set of fields -------------------------------------------------------
@@ -388,8 +378,6 @@ struct LaunchSet {
     Fields cls[kClasses];
     bool used[kClasses];
     unsigned grid_s[kClasses], grid_j[kClasses];
-    uint32_t regions;             // host total of chase tiles (all classes)
-    const uint32_t* regions_dev;  // or on the device
     bool capacity;                // grids sized for a capacity, totals on the device
     int bn;
     int32_t dtype;
@@ -432,11 +420,11 @@ void launch_chase_cls(int c, const Fields& F, unsigned grid, uint32_t* U, uint32
     uint64_t* rec = reinterpret_cast<uint64_t*>(w.keys[1]);
     launch(PLMSS_KERNEL_JUMP, s, [&] {
         if (c == 0)
-            k_chase<JTile3, CHASE><<<grid, kBlock, 0, s>>>(F, U, D, bn, rec, w.reg_cnt);
+            k_chase<JTile3, CHASE><<<grid, kBlock, 0, s>>>(F, U, D, bn, rec, w.vals[0], w.counters + 0);
         else if (c == 1)
-            k_chase<JTile2, CHASE><<<grid, kBlock, 0, s>>>(F, U, D, bn, rec, w.reg_cnt);
+            k_chase<JTile2, CHASE><<<grid, kBlock, 0, s>>>(F, U, D, bn, rec, w.vals[0], w.counters + 0);
         else
-            k_chase<JTile1, CHASE><<<grid, kBlock, 0, s>>>(F, U, D, bn, rec, w.reg_cnt);
+            k_chase<JTile1, CHASE><<<grid, kBlock, 0, s>>>(F, U, D, bn, rec, w.vals[0], w.counters + 0);
     });
 }
 
@@ -444,34 +432,27 @@ void launch_ms_final_cls(int c, const Fields& F, unsigned grid, const Work& w, h
     if (grid == 0) return;
     launch(PLMSS_KERNEL_MS_FINAL, s, [&] {
         if (c == 0)
-            k_ms_final<JTile3><<<grid, kBlock, 0, s>>>(F, w.reg_off, w.rank_of, w.fbase);
+            k_ms_final<JTile3><<<grid, kBlock, 0, s>>>(F, w.rank_of, w.fbase);
         else if (c == 1)
-            k_ms_final<JTile2><<<grid, kBlock, 0, s>>>(F, w.reg_off, w.rank_of, w.fbase);
+            k_ms_final<JTile2><<<grid, kBlock, 0, s>>>(F, w.rank_of, w.fbase);
         else
-            k_ms_final<JTile1><<<grid, kBlock, 0, s>>>(F, w.reg_off, w.rank_of, w.fbase);
+            k_ms_final<JTile1><<<grid, kBlock, 0, s>>>(F, w.rank_of, w.fbase);
     });
 }
 
-// MS ids from the pairs listed per chase tile: compact, sort, rank, per-field
-// bases, relabel.
+// MS ids from the pairs the chase listed: sort, rank, per-field bases,
+// relabel.
 void ms_from_pairs(const LaunchSet& L, const Work& w, hipStream_t s) {
-    uint64_t* rec = reinterpret_cast<uint64_t*>(w.keys[1]);
-    prefix_sum(w.reg_cnt, L.regions_dev, L.regions, w.reg_off, w.counters + 0, w, s);
-    const unsigned cgrid = L.capacity ? persist_blocks() : std::max(1u, L.regions);
-    launch(PLMSS_KERNEL_COMPACT, s, [&] {
-        k_compact_pairs<<<cgrid, kBlock, 0, s>>>(w.reg_cnt, w.reg_off, L.regions_dev, L.regions, rec,
-                                                 reinterpret_cast<uint64_t*>(w.keys[0]), w.vals[0]);
-    });
-    const int r = sort_pairs(2 * L.bn, w, s);
-    const uint64_t* sk = reinterpret_cast<const uint64_t*>(w.keys[r]);
+    const PairList sorted = sort_pairs(2 * L.bn, w, s);
+    const uint64_t* sk = sorted.keys;
     const unsigned nw = sort_workers();
     launch(PLMSS_KERNEL_RANK, s, [&] { k_rank_reduce<<<nw, kBlock, 0, s>>>(sk, w.counters + 0, w.partial); });
     launch(PLMSS_KERNEL_PREFIX, s, [&] { k_scan_partials<<<1, kBlock, 0, s>>>(w.partial, int(nw), w.counters + 1); });
     launch(PLMSS_KERNEL_RANK, s, [&] {
-        k_rank_apply<<<nw, kBlock, 0, s>>>(sk, w.vals[r], w.counters + 0, w.partial, w.rank_of);
+        k_rank_apply<<<nw, kBlock, 0, s>>>(sk, sorted.vals, w.counters + 0, w.partial, w.rank_of);
     });
     launch(PLMSS_KERNEL_RANK, s, [&] {
-        k_field_base<<<1, kBlock, 0, s>>>(L.all, sk, w.vals[r], w.counters + 0, w.counters + 1, w.rank_of,
+        k_field_base<<<1, kBlock, 0, s>>>(L.all, sk, sorted.vals, w.counters + 0, w.counters + 1, w.rank_of,
                                           L.bn, w.fbase);
     });
     for (int c = 0; c < kClasses; ++c)
@@ -540,8 +521,6 @@ LaunchSet single_set(const plmss_job& job, uint64_t n, int zc) {
     L.cls[c] = fields_one(d, st, jt);
     L.grid_s[c] = st;
     L.grid_j[c] = jt;
-    L.regions = jt;
-    L.regions_dev = nullptr;
     L.capacity = false;
     L.bn = id_bits(n);
     L.dtype = job.dtype;
@@ -582,11 +561,10 @@ int batch_layout(int32_t n_jobs, const plmss_job* jobs, int zc, BatchLayout* B) 
         B->s_tiles[c] += s_tiles_of(jobs[i].dims, zc);
         B->j_tiles[c] += j_tiles_of(jobs[i].dims);
     }
-    // pair-list regions: class 0 tiles first, then class 1, then class 2
+    // chase tiles: class 0 first, then class 1, then class 2
     B->region0[1] = B->j_tiles[0];
     B->region0[2] = B->j_tiles[0] + B->j_tiles[1];
     B->regions = uint64_t(B->j_tiles[0]) + B->j_tiles[1] + B->j_tiles[2];
-    if (B->regions * kJV > 0xffffffffull) return PLMSS_E_TOO_LARGE;
     return PLMSS_OK;
 }
 
@@ -617,8 +595,6 @@ LaunchSet batch_set(const BatchLayout& B, const FieldDesc* tables, size_t stride
         L.grid_s[c] = B.s_tiles[c];
         L.grid_j[c] = B.j_tiles[c];
     }
-    L.regions = uint32_t(B.regions);
-    L.regions_dev = nullptr;
     L.capacity = false;
     L.bn = bn;
     L.dtype = dtype;
@@ -629,11 +605,10 @@ LaunchSet batch_set(const BatchLayout& B, const FieldDesc* tables, size_t stride
 // Device totals block of a capacity launch (u32, in counters[32..63]):
 //   [4c .. 4c+3]  class c: scan tiles, chase tiles, fields, first region
 //   [12 .. 15]    all fields: 0, 0, fields, 0
-//   [16]          regions (all classes)
 constexpr int kTot = 32;
 
-LaunchSet capacity_set(const Work& w, size_t stride, unsigned grid_s, unsigned grid_j, uint32_t max_regions,
-                       int32_t dtype, int bn, int zc) {
+LaunchSet capacity_set(const Work& w, size_t stride, unsigned grid_s, unsigned grid_j, int32_t dtype, int bn,
+                       int zc) {
     const uint32_t* tot = w.counters + kTot;
     LaunchSet L{};
     L.all = Fields{};
@@ -650,8 +625,6 @@ LaunchSet capacity_set(const Work& w, size_t stride, unsigned grid_s, unsigned g
         L.grid_s[c] = grid_s;
         L.grid_j[c] = grid_j;
     }
-    L.regions = max_regions;
-    L.regions_dev = tot + 16;
     L.capacity = true;
     L.bn = bn;
     L.dtype = dtype;
@@ -706,7 +679,7 @@ size_t plmss_workspace_bytes(plmss_dims dims, int32_t dtype, int32_t with_order)
     if (check_dims(dims, &n) != PLMSS_OK) return 0;
     (void)dtype;
     (void)with_order;
-    return work_sizes(n, j_tiles_of(dims), 1, 0).total;
+    return work_sizes(n, 1, 0).total;
 }
 
 int plmss_segment(const plmss_job* job, void* workspace, size_t workspace_bytes, void* stream) {
@@ -715,8 +688,7 @@ int plmss_segment(const plmss_job* job, void* workspace, size_t workspace_bytes,
     uint64_t n;
     int rc = check_dims(job->dims, &n);
     if (rc) return rc;
-    if (uint64_t(j_tiles_of(job->dims)) * kJV > 0xffffffffull) return PLMSS_E_TOO_LARGE;
-    const Sizes sz = work_sizes(n, j_tiles_of(job->dims), 1, 0);
+    const Sizes sz = work_sizes(n, 1, 0);
     if (!ws_ok(workspace, workspace_bytes, sz.total)) return PLMSS_E_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const Work w = carve(workspace, sz);
@@ -735,7 +707,7 @@ int plmss_order_field(const void* field, plmss_dims dims, int32_t dtype, int32_t
     uint64_t n;
     int rc = check_dims(dims, &n);
     if (rc) return rc;
-    const Sizes sz = work_sizes(n, j_tiles_of(dims), 1, 0);
+    const Sizes sz = work_sizes(n, 1, 0);
     if (!ws_ok(workspace, workspace_bytes, sz.total)) return PLMSS_E_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const Work w = carve(workspace, sz);
@@ -776,8 +748,7 @@ int plmss_compress(int32_t* desc, int32_t* asc, int64_t n, void* stream) {
 
 size_t plmss_ms_workspace_bytes(int64_t n) {
     if (n < 1 || n > kMaxN) return 0;
-    const plmss_dims d{n, 1, 1};
-    return work_sizes(uint64_t(n), j_tiles_of(d), 1, 0).total;
+    return work_sizes(uint64_t(n), 1, 0).total;
 }
 
 int plmss_ms_ids(const int32_t* asc, const int32_t* desc, int64_t n, int32_t* ms, int32_t* info,
@@ -786,7 +757,7 @@ int plmss_ms_ids(const int32_t* asc, const int32_t* desc, int64_t n, int32_t* ms
     if (n < 1) return PLMSS_E_DIMS;
     if (n > kMaxN) return PLMSS_E_TOO_LARGE;
     const plmss_dims d{n, 1, 1};
-    const Sizes sz = work_sizes(uint64_t(n), j_tiles_of(d), 1, 0);
+    const Sizes sz = work_sizes(uint64_t(n), 1, 0);
     if (!ws_ok(workspace, workspace_bytes, sz.total)) return PLMSS_E_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const Work w = carve(workspace, sz);
@@ -807,7 +778,7 @@ int plmss_ms_ids(const int32_t* asc, const int32_t* desc, int64_t n, int32_t* ms
 size_t plmss_batch_workspace_bytes(int32_t n_jobs, const plmss_job* jobs) {
     BatchLayout B;
     if (batch_layout(n_jobs, jobs, scan_depth(), &B) != PLMSS_OK) return 0;
-    return work_sizes(B.nv, B.regions, uint64_t(n_jobs), uint64_t(n_jobs)).total;
+    return work_sizes(B.nv, uint64_t(n_jobs), uint64_t(n_jobs)).total;
 }
 
 int plmss_segment_batch(int32_t n_jobs, const plmss_job* jobs, void* workspace,
@@ -815,7 +786,7 @@ int plmss_segment_batch(int32_t n_jobs, const plmss_job* jobs, void* workspace,
     BatchLayout B;
     int rc = batch_layout(n_jobs, jobs, scan_depth(), &B);
     if (rc) return rc;
-    const Sizes sz = work_sizes(B.nv, B.regions, uint64_t(n_jobs), uint64_t(n_jobs));
+    const Sizes sz = work_sizes(B.nv, uint64_t(n_jobs), uint64_t(n_jobs));
     if (!ws_ok(workspace, workspace_bytes, sz.total)) return PLMSS_E_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const Work w = carve(workspace, sz);
@@ -847,7 +818,6 @@ plmss_plan* plmss_plan_create(int64_t max_vertices, int32_t max_fields, int64_t 
     if (max_vertices < 1 || max_vertices > kMaxN || max_fields < 1 || max_scan_tiles < 1 ||
         max_chase_tiles < 1 || (dtype != PLMSS_F32 && dtype != PLMSS_F64))
         return nullptr;
-    if (uint64_t(max_chase_tiles) * kJV > 0xffffffffull) return nullptr;
     plmss_plan* p = new (std::nothrow) plmss_plan;
     if (!p) return nullptr;
     p->max_vertices = max_vertices;
@@ -857,7 +827,7 @@ plmss_plan* plmss_plan_create(int64_t max_vertices, int32_t max_fields, int64_t 
     p->dtype = dtype;
     p->bn = id_bits(uint64_t(max_vertices));
     p->zc = scan_depth();
-    p->sizes = work_sizes(uint64_t(max_vertices), uint64_t(max_chase_tiles), uint64_t(max_fields),
+    p->sizes = work_sizes(uint64_t(max_vertices), uint64_t(max_fields),
                           uint64_t(max_fields));
     if (hipHostMalloc(reinterpret_cast<void**>(&p->pinned), sizeof(FieldDesc) * 4 * size_t(max_fields)) !=
         hipSuccess) {
@@ -910,7 +880,6 @@ int plmss_plan_set(plmss_plan* p, int32_t n_jobs, const plmss_job* jobs, void* w
         tot[4 * c + 3] = B.region0[c];
     }
     tot[14] = uint32_t(n_jobs);
-    tot[16] = uint32_t(B.regions);
     if (hipMemcpyAsync(w.tables, p->pinned, sizeof(FieldDesc) * img.size(), hipMemcpyHostToDevice, s) !=
         hipSuccess)
         return PLMSS_E_HIP;
@@ -927,7 +896,7 @@ int plmss_plan_launch(plmss_plan* p, void* workspace, size_t workspace_bytes, vo
     const unsigned gs = unsigned(std::min<int64_t>(persist_blocks(), p->max_scan_tiles));
     const unsigned gj = unsigned(std::min<int64_t>(persist_blocks(), p->max_chase_tiles));
     const LaunchSet L =
-        capacity_set(w, size_t(p->max_fields), gs, gj, uint32_t(p->max_chase_tiles), p->dtype, p->bn, p->zc);
+        capacity_set(w, size_t(p->max_fields), gs, gj, p->dtype, p->bn, p->zc);
     run_set(L, nullptr, nullptr, 0, w, s);
     return launch_status();
 }

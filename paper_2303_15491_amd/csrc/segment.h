@@ -548,10 +548,12 @@ inline uint32_t steepest_tiles(int64_t nx, int64_t ny, int64_t nz, int ty, int z
 // is followed from tile to tile (each hop lands on the next tile's compressed
 // pointer, and is written back so that later readers jump further) until a
 // marked extremum.  It writes desc/asc, then lists the tile's distinct
-// (asc, desc) pairs through an LDS hash set: keys (asc << bn) | desc go to
-// rec[kJV*tile + j], j < reg_cnt[tile], and each vertex's slot kJV*tile + j to
-// ms[v] (replaced by the MS id later).  MS regions are a few vertices across,
-// so a 3-D tile lists far fewer pairs than a row of the same size would.
+// (asc, desc) pairs through an LDS hash set: the tile takes a run of
+// consecutive record indices from a launch-wide counter (one atomic add per
+// tile), writes each pair key (asc << bn) | desc to rec_keys and its record
+// index to rec_vals, and stores each vertex's record index in ms[v] (replaced
+// by the MS id later).  MS regions are a few vertices across, so a 3-D tile
+// lists far fewer pairs than a row of the same size would.
 constexpr int kJV = 2048;            // vertices per tile
 constexpr int kJPer = kJV / kBlock;  // per thread
 constexpr int kHash = kJV;           // hash slots: a tile has at most kJV distinct pairs
@@ -593,10 +595,11 @@ __device__ __forceinline__ void jtile_xyz(const FieldDesc& fd, uint32_t lt, int 
 // are followed).  Otherwise the labels are read from the field's desc/asc.
 template <class T, bool CHASE>
 __global__ __launch_bounds__(kBlock) void k_chase(Fields F, uint32_t* U, uint32_t* D, int bn,
-                                                  uint64_t* rec, uint32_t* reg_cnt) {
+                                                  uint64_t* rec_keys, uint32_t* rec_vals, uint32_t* rec_count) {
     __shared__ uint64_t table[kHash];
     __shared__ uint16_t dense[kHash];
     __shared__ uint32_t tmp[kWavesPerBlock];
+    __shared__ uint32_t s_base;
     const int t = threadIdx.x, lane = lane_id(), w = wave_id();
     uint32_t tfirst, tlast;
     block_tiles(F.dev_tiles ? gmem(F.dev_tiles)[1] : F.j_tiles, &tfirst, &tlast);
@@ -696,7 +699,9 @@ __global__ __launch_bounds__(kBlock) void k_chase(Fields F, uint32_t* U, uint32_
             j += (i < w) ? tmp[i] : 0u;
             total += tmp[i];
         }
-        const size_t region = size_t(fields_region0(F) + tile) * kJV;
+        if (t == 0) s_base = atomicAdd(rec_count, total);
+        __syncthreads();
+        const uint32_t base = s_base;
 #pragma unroll
         for (int i = 0; i < kRows; ++i) {
             const int sl = w * (kHash / kWavesPerBlock) + i * kWave + lane;
@@ -705,15 +710,15 @@ __global__ __launch_bounds__(kBlock) void k_chase(Fields F, uint32_t* U, uint32_
             if (k != kEmpty) {
                 const uint32_t jj = j + uint32_t(__popcll(occ & lt_mask));
                 dense[sl] = uint16_t(jj);
-                rec[region + jj] = k;
+                rec_keys[base + jj] = k;
+                rec_vals[base + jj] = base + jj;
             }
             j += uint32_t(__popcll(occ));
         }
-        if (t == 0) reg_cnt[fields_region0(F) + tile] = total;
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < kJPer; ++i)
-            if (ok[i]) gmem(fd.ms)[lv[i]] = int32_t(uint32_t(region) + dense[slot[i]]);
+            if (ok[i]) gmem(fd.ms)[lv[i]] = int32_t(base + dense[slot[i]]);
         (void)fidx;
     }
 }
@@ -754,25 +759,7 @@ __global__ __launch_bounds__(kBlock) void k_jump(int32_t* desc, int32_t* asc, ui
     }
 }
 
-// ---- pair compaction and ranking ------------------------------------------------------
-
-// One block per tile region (a persistent loop when the region count lives
-// on the device): copy its listed pairs to the dense arrays at off[region]
-// (exclusive prefix of reg_cnt): keys[o + j] = pair, vals[o + j] = o + j (the
-// dense index travels with the key through the sort).
-__global__ __launch_bounds__(kBlock) void k_compact_pairs(const uint32_t* reg_cnt,
-                                                          const uint32_t* off, const uint32_t* count_ptr,
-                                                          uint32_t nregions, const uint64_t* rec,
-                                                          uint64_t* keys, uint32_t* vals) {
-    const uint32_t m = load_count(count_ptr, nregions);
-    for (uint32_t r = blockIdx.x; r < m; r += gridDim.x) {
-        const uint32_t c = reg_cnt[r], o = off[r];
-        for (uint32_t j = threadIdx.x; j < c; j += kBlock) {
-            keys[o + j] = rec[size_t(r) * kJV + j];
-            vals[o + j] = o + j;
-        }
-    }
-}
+// ---- pair ranking ---------------------------------------------------------------------
 
 // flag[i] = (i == 0 || key[i] != key[i-1]); rank[i] = (flags in 0..i) - 1.
 __device__ __forceinline__ uint32_t pair_flag(const uint64_t* keys, uint32_t i) {
@@ -826,12 +813,11 @@ __global__ __launch_bounds__(kBlock) void k_rank_apply(const uint64_t* keys, con
     }
 }
 
-// ms[v] = MS id of its listed pair: rank_of[off[slot / kJV] + slot % kJV]
-// minus the field's first id, with slot = ms[v] on entry.  Runs over the chase
-// tiles, so every block knows its field.
+// ms[v] = MS id of its listed pair: rank_of[record] minus the field's first
+// id, with the record index in ms[v] on entry.  Runs over the chase tiles, so
+// every block knows its field.
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_ms_final(Fields F, const uint32_t* off,
-                                                     const uint32_t* rank_of, const uint32_t* fbase) {
+__global__ __launch_bounds__(kBlock) void k_ms_final(Fields F, const uint32_t* rank_of, const uint32_t* fbase) {
     uint32_t tfirst, tlast;
     block_tiles(F.dev_tiles ? gmem(F.dev_tiles)[1] : F.j_tiles, &tfirst, &tlast);
     for (uint32_t tile = tfirst; tile < tlast; ++tile) {
@@ -851,7 +837,7 @@ __global__ __launch_bounds__(kBlock) void k_ms_final(Fields F, const uint32_t* o
         }
 #pragma unroll
         for (int i = 0; i < kJPer; ++i)
-            if (ok[i]) gmem(fd.ms)[lv[i]] = int32_t(rank_of[off[sl[i] / kJV] + sl[i] % kJV] - base);
+            if (ok[i]) gmem(fd.ms)[lv[i]] = int32_t(rank_of[sl[i]] - base);
     }
 }
 

@@ -574,26 +574,6 @@ __global__ __launch_bounds__(kBlock) void k_invert(const uint32_t* ids, uint32_t
 
 // ---- device-wide exclusive prefix sums over uint32 ---------------------------------
 
-// partial[b] = sum of in[lo..hi) over worker b's slice (slices of kTile).
-__global__ __launch_bounds__(kBlock) void k_sum_reduce(const uint32_t* in,
-                                                       const uint32_t* count_ptr, uint32_t n,
-                                                       uint32_t* partial) {
-    __shared__ uint32_t tmp[kWavesPerBlock];
-    uint32_t lo, hi;
-    worker_range(load_count(count_ptr, n), blockIdx.x, gridDim.x, kTile, &lo, &hi);
-    uint32_t s = 0;
-    for (uint32_t tile = lo; tile < hi; tile += kTile) {
-#pragma unroll
-        for (int i = 0; i < kItems; ++i) {
-            const uint32_t idx = tile + uint32_t(i) * kBlock + threadIdx.x;
-            s += idx < hi ? in[idx] : 0u;
-        }
-    }
-    uint32_t tot;
-    block_exclusive_scan(s, tmp, &tot);
-    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
-}
-
 // One block: exclusive scan of partial[0..m) in place; *total = the sum.
 __global__ __launch_bounds__(kBlock) void k_scan_partials(uint32_t* partial, int m,
                                                           uint32_t* total) {
@@ -613,34 +593,6 @@ __global__ __launch_bounds__(kBlock) void k_scan_partials(uint32_t* partial, int
         }
     }
     if (threadIdx.x == 0 && total) *total = tot;
-}
-
-// out[i] = exclusive prefix of in[] (worker slices of kTile, offsets from
-// partial[]).  Each thread sums kItems consecutive entries.
-__global__ __launch_bounds__(kBlock) void k_scan_apply(const uint32_t* in, const uint32_t* count_ptr,
-                                                       uint32_t n, const uint32_t* partial,
-                                                       uint32_t* out) {
-    __shared__ uint32_t tmp[kWavesPerBlock];
-    uint32_t lo, hi;
-    worker_range(load_count(count_ptr, n), blockIdx.x, gridDim.x, kTile, &lo, &hi);
-    uint32_t run = partial[blockIdx.x];
-    for (uint32_t tile = lo; tile < hi; tile += kTile) {
-        const uint32_t beg = tile + threadIdx.x * kItems;
-        uint32_t c[kItems], s = 0;
-#pragma unroll
-        for (int i = 0; i < kItems; ++i) {
-            c[i] = beg + i < hi ? in[beg + i] : 0u;
-            s += c[i];
-        }
-        uint32_t tot;
-        uint32_t e = run + block_exclusive_scan(s, tmp, &tot);
-#pragma unroll
-        for (int i = 0; i < kItems; ++i) {
-            if (beg + i < hi) out[beg + i] = e;
-            e += c[i];
-        }
-        run += tot;
-    }
 }
 
 }  // namespace plmss
