@@ -33,7 +33,7 @@ SPACE = {
     "scan_rounds": [3, 2, 4],
     "sort_workers": [256, 512, 1024, 2048, 4096],
     "scan_depth": [8, 16, 32],
-    "persist_blocks": [512, 1024, 2048, 4096, 8192],
+    "persist_blocks": [512, 1024, 2048, 4096, 8192, 16384],
 }
 
 SEGMENT_KNOBS = ("scan_depth", "scan_rounds", "sort_workers")

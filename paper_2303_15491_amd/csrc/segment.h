@@ -126,6 +126,41 @@ __device__ __forceinline__ FieldDesc field_of_tile(const Fields& F, uint32_t til
     return load_desc(F.table, lo);
 }
 
+// The field of each tile of a block's run of consecutive tiles: one binary
+// search for the run's first tile, then a step to the next field each time a
+// tile reaches that field's first tile (the descriptor is reloaded only
+// then), instead of a search through the table in global memory per tile.
+template <bool STEEP>
+struct FieldCursor {
+    const FieldDesc* table;
+    uint32_t idx = 0, count = 0, next = 0;
+    bool started = false;
+    FieldDesc fd;
+    __device__ explicit FieldCursor(const Fields& F) : table(F.table) {
+        if (!table) fd = F.one;
+    }
+    __device__ __forceinline__ uint32_t base(uint32_t i) const {
+        return STEEP ? gmem(table)[i].sbase : gmem(table)[i].jbase;
+    }
+    // Tiles must come in increasing order.
+    __device__ __forceinline__ FieldDesc at(const Fields& F, uint32_t tile) {
+        if (!table) return fd;
+        if (!started) {
+            fd = field_of_tile<STEEP>(F, tile, &idx);
+            count = fields_count(F);
+            next = idx + 1 < count ? base(idx + 1) : ~0u;
+            started = true;
+        } else if (tile >= next) {
+            do {
+                ++idx;
+                next = idx + 1 < count ? base(idx + 1) : ~0u;
+            } while (tile >= next);
+            fd = load_desc(table, idx);
+        }
+        return fd;
+    }
+};
+
 // This block's tiles: a contiguous run, so that each XCD works on a compact
 // part of the grid.
 __device__ __forceinline__ void block_tiles(uint32_t total, uint32_t* first, uint32_t* last) {
@@ -268,9 +303,9 @@ __global__ __launch_bounds__(kBlock) void k_steepest(Fields F, uint32_t* up, uin
     const uint32_t xside = (lane == 0 ? 1u : 0u) | (lane == kTX - 1 ? 2u : 0u);
     uint32_t tfirst, tlast;
     block_tiles(F.dev_tiles ? gmem(F.dev_tiles)[0] : F.s_tiles, &tfirst, &tlast);
+    FieldCursor<true> cursor(F);
     for (uint32_t tile = tfirst; tile < tlast; ++tile) {
-    uint32_t fidx;
-    const FieldDesc fd = field_of_tile<true>(F, tile, &fidx);
+    const FieldDesc fd = cursor.at(F, tile);
     const Src src = Src::from(fd.src);
     const GridDims g{fd.nx, fd.ny, fd.nz};
     int32_t* const info = fd.info;
@@ -533,7 +568,6 @@ __global__ __launch_bounds__(kBlock) void k_steepest(Fields F, uint32_t* up, uin
         if (cnt_max) atomicAdd(reinterpret_cast<uint32_t*>(info + 2), cnt_max);
         if (nan_seen) info[0] = -4;  // PLMSS_E_NAN
     }
-    (void)fidx;
     }  // tiles
 }
 
@@ -603,9 +637,9 @@ __global__ __launch_bounds__(kBlock) void k_chase(Fields F, uint32_t* U, uint32_
     const int t = threadIdx.x, lane = lane_id(), w = wave_id();
     uint32_t tfirst, tlast;
     block_tiles(F.dev_tiles ? gmem(F.dev_tiles)[1] : F.j_tiles, &tfirst, &tlast);
+    FieldCursor<false> cursor(F);
     for (uint32_t tile = tfirst; tile < tlast; ++tile) {
-        uint32_t fidx;
-        const FieldDesc fd = field_of_tile<false>(F, tile, &fidx);
+        const FieldDesc fd = cursor.at(F, tile);
         const uint32_t lt = tile - fd.jbase;
         __syncthreads();  // the previous tile's readers of LDS are done
 #pragma unroll
@@ -719,7 +753,6 @@ __global__ __launch_bounds__(kBlock) void k_chase(Fields F, uint32_t* U, uint32_
 #pragma unroll
         for (int i = 0; i < kJPer; ++i)
             if (ok[i]) gmem(fd.ms)[lv[i]] = int32_t(base + dense[slot[i]]);
-        (void)fidx;
     }
 }
 
@@ -820,9 +853,9 @@ template <class T>
 __global__ __launch_bounds__(kBlock) void k_ms_final(Fields F, const uint32_t* rank_of, const uint32_t* fbase) {
     uint32_t tfirst, tlast;
     block_tiles(F.dev_tiles ? gmem(F.dev_tiles)[1] : F.j_tiles, &tfirst, &tlast);
+    FieldCursor<false> cursor(F);
     for (uint32_t tile = tfirst; tile < tlast; ++tile) {
-        uint32_t fidx;
-        const FieldDesc fd = field_of_tile<false>(F, tile, &fidx);
+        const FieldDesc fd = cursor.at(F, tile);
         const uint32_t lt = tile - fd.jbase;
         const uint32_t base = fbase ? fbase[fd.index] : 0u;
         uint32_t lv[kJPer], sl[kJPer];
