@@ -52,6 +52,56 @@ def algo_bytes(kind: str, invert: int):
     return ALGO_BYTES.get(kind)
 
 
+# Launch-shape knobs each kernel kind depends on (a traffic profile taken
+# with other values of these does not describe the kernel that ran).
+KIND_KNOBS = {"steepest": ("scan_depth", "scan_rounds"), "jump": ("scan_depth", "scan_rounds"),
+              "ms_final": ("scan_depth", "scan_rounds")}
+for _k in ("order_first", "order_scatter", "order_last", "order_regroup", "order_invert", "order_hist"):
+    KIND_KNOBS[_k] = ("order_workers", "order_invert", "order_packed")
+for _k in ("radix_hist", "radix_scatter", "radix_digit_scan", "pair_rank"):
+    KIND_KNOBS[_k] = ("sort_workers",)
+
+
+def kernel_source_digest() -> str:
+    """Digest of the kernel sources: a traffic profile holds only for the code it was taken on."""
+    import glob
+    import hashlib
+
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2303_15491_amd", "csrc", "*")))
+    files.append(os.path.join(ROOT, "include", "plmss.h"))
+    for path in files:
+        with open(path, "rb") as fh:
+            h.update(os.path.basename(path).encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(workload: str, kind: str, knobs: dict):
+    """HBM bytes per launch of `kind` from the committed rocprofv3 counter
+    summary of this workload, or (None, reason)."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
+    try:
+        with open(path) as fh:
+            text = fh.read()
+    except OSError:
+        return None, "no counter profile for this workload"
+    start = text.find("```json")
+    end = text.find("```", start + 7)
+    if start < 0 or end < 0:
+        return None, "counter profile has no data block"
+    data = json.loads(text[start + 7:end])
+    if data.get("source_digest") != kernel_source_digest():
+        return None, "kernels changed since the counters were taken"
+    for k in KIND_KNOBS.get(kind, ()):
+        if data.get("knobs", {}).get(k) != knobs.get(k):
+            return None, f"counters were taken with {k}={data.get('knobs', {}).get(k)}, this run used {knobs.get(k)}"
+    entry = data.get("kinds", {}).get(kind)
+    if not entry:
+        return None, f"no counters for {kind}"
+    return entry["hbm_bytes_per_launch"], path
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -321,9 +371,12 @@ def main():
         per_launch_bytes = None
         basis = "n/a"
     achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9 if per_launch_bytes else None
+    traffic, traffic_src = profiled_traffic(args.workload, dom, knobs)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
-                "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": per_launch_bytes, "basis": basis}
+                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
+                "traffic_source": traffic_src, "avg_launch_ms": avg_ms,
+                "algorithmic_bytes_per_launch": per_launch_bytes, "basis": basis,
+                "kernel_source_digest": kernel_source_digest()}
 
     # CPU baseline: the oracle on a bounded slab of the same field, one core
     cpu = None

@@ -244,7 +244,7 @@ const char* plmss_kernel_name(int32_t kind);
  *                              neighbour scan (1..8, default 3); what they
  *                              leave unfinished the cross-tile chase follows.
  *   PLMSS_TUNE_SORT_WORKERS    blocks of device-sized sorts and scans (the MS
- *                              pair sort): 64..4096, default 1024.
+ *                              pair sort): 64..4096, default 512.
  *   PLMSS_TUNE_PERSIST_BLOCKS  grid of a plan's persistent launches:
  *                              64..16384, default 2048.
  *   PLMSS_TUNE_SCAN_DEPTH      z-planes of a 3-D neighbour-scan tile (each

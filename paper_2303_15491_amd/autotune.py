@@ -12,7 +12,8 @@ other, and the best values depend on the field's size and shape.
 inputs (coordinate descent: one knob at a time, the others held, each
 candidate timed with HIP events over a few repetitions, the median kept),
 check that every candidate produces exactly the labels of the starting
-configuration, leave the winners set, and remember them in a JSON cache keyed
+configuration, keep a candidate only when it is at least 2% faster, leave the
+winners set, and remember them in a JSON cache keyed
 by GPU architecture, element type, workload kind, dimensionality and size
 bucket (log2 of the vertex count).  ``apply`` sets cached values without
 timing anything.
@@ -31,7 +32,7 @@ SPACE = {
     "order_invert": [1, 0, 2, 4],
     "order_packed": [0, 1],
     "scan_rounds": [3, 2, 4],
-    "sort_workers": [256, 512, 1024, 2048, 4096],
+    "sort_workers": [512, 256, 1024, 2048, 4096],
     "scan_depth": [8, 16, 32],
     "persist_blocks": [512, 1024, 2048, 4096, 8192, 16384],
 }
@@ -39,6 +40,10 @@ SPACE = {
 SEGMENT_KNOBS = ("scan_depth", "scan_rounds", "sort_workers")
 ORDER_KNOBS = ("order_invert", "order_packed", "order_workers")
 BATCH_KNOBS = ("persist_blocks", "scan_depth", "scan_rounds", "sort_workers")
+
+# a candidate replaces the current setting only when it is this much faster,
+# so that timing noise does not flip settings from run to run
+MIN_GAIN = 0.02
 
 _lock = threading.Lock()
 
@@ -136,7 +141,7 @@ def _descend(torch, knobs, run, result, reps: int, log=None):
             trials.append({"knobs": cand, "ms": ms})
             if log:
                 log(f"tune {cand}: {ms:.3f} ms")
-            if ms < best_ms:
+            if ms < best_ms * (1.0 - MIN_GAIN):
                 best, best_ms = cand, ms
         tune_set(**best)
     return best, best_ms, base_ms, trials

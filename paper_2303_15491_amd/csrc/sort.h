@@ -20,7 +20,7 @@ constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;  // == kBlock: one thread per digit
 constexpr int kItems = 16;               // keys per thread per tile
 constexpr int kTile = kBlock * kItems;
-constexpr int kWorkers = 1024;           // default grid of device-sized sorts and scans
+constexpr int kWorkers = 512;            // default grid of device-sized sorts and scans
 constexpr int kMaxWorkers = 4096;        // largest such grid (sizes the workspace)
 static_assert(kRadix == kBlock, "one thread per digit");
 
