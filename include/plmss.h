@@ -238,8 +238,10 @@ const char* plmss_kernel_name(int32_t kind);
  *                              2..64 = the last pass writes the sorted ids and
  *                              w launches invert them, each for 1/w of the id
  *                              range.
- *   PLMSS_TUNE_ORDER_PACKED    1 = 32-bit keys travel packed with their ids
- *                              in one 64-bit word; 0 (default) = two arrays.
+ *   PLMSS_TUNE_ORDER_PACKED    1 (default) = 32-bit keys travel packed with
+ *                              their ids in one 64-bit word until the last
+ *                              pass, which reads them as two arrays; 0 = two
+ *                              arrays throughout.
  *   PLMSS_TUNE_SCAN_ROUNDS     in-tile path-compression sweeps of the
  *                              neighbour scan (1..8, default 3); what they
  *                              leave unfinished the cross-tile chase follows.

@@ -30,7 +30,7 @@ from . import KNOBS, Plan, PlmssError, batch_needs, segment, tune_get, tune_set
 SPACE = {
     "order_workers": [8192, 4096, 16384, 0],
     "order_invert": [1, 0, 2, 4],
-    "order_packed": [0, 1],
+    "order_packed": [1, 0],
     "scan_rounds": [3, 2, 4],
     "sort_workers": [512, 256, 1024, 2048, 4096],
     "scan_depth": [8, 16, 32],

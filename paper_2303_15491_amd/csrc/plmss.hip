@@ -31,7 +31,7 @@ constexpr KnobRange kKnobs[PLMSS_TUNE_KNOBS] = {
     {64, kMaxWorkers, kWorkers, false, false},  // SORT_WORKERS
     {64, 16384, 2048, false, false},           // PERSIST_BLOCKS
     {8, 32, 16, false, true},                  // SCAN_DEPTH: 8, 16 or 32 planes
-    {1, 1, 0, true, false},                    // ORDER_PACKED: 32-bit keys packed with ids
+    {1, 1, 1, true, false},                    // ORDER_PACKED: 32-bit keys packed with ids
     {1, 8, kResolveRounds, false, false},      // SCAN_ROUNDS: in-tile jumping sweeps
 };
 std::atomic<int64_t> g_knob[PLMSS_TUNE_KNOBS] = {kKnobs[0].def, kKnobs[1].def, kKnobs[2].def,
@@ -226,12 +226,24 @@ void radix_pass(Src src, Dst dst, const uint32_t* cnt, uint32_t n, unsigned work
 }
 
 // Ping-pong storage of the order sort's (key, id) items: 32-bit keys packed
-// with their ids in one word, or keys and ids in two arrays.
+// with their ids in one word, or keys and ids in two arrays.  The packed form
+// halves the write streams of a scatter, the split form halves what a
+// histogram reads; so the packed storage turns split for the last pass (the
+// pass before it writes keys and ids into the two halves of one buffer).
 struct PackedItems {
     uint64_t* kv[2];
     uint32_t* ids_buf;
+    uint64_t npad;
     PackedSrc src(int c) const { return {kv[c]}; }
     PackedDst dst(int c) const { return {kv[c]}; }
+    ArrayDst<uint32_t> split_dst(int c) const {
+        uint32_t* k = reinterpret_cast<uint32_t*>(kv[c]);
+        return {k, k + npad};
+    }
+    ArraySrc<uint32_t> last_src(int c) const {
+        const uint32_t* k = reinterpret_cast<const uint32_t*>(kv[c]);
+        return {k, k + npad};
+    }
     uint64_t* spare(int c) const { return kv[c ^ 1]; }
     uint64_t* own(int c) const { return kv[c]; }
     uint32_t* ids(int) const { return ids_buf; }
@@ -243,6 +255,8 @@ struct SplitItems {
     uint32_t* vals[2];
     ArraySrc<K> src(int c) const { return {keys[c], vals[c]}; }
     ArrayDst<K> dst(int c) const { return {keys[c], vals[c]}; }
+    ArrayDst<K> split_dst(int c) const { return dst(c); }
+    ArraySrc<K> last_src(int c) const { return src(c); }
     uint64_t* spare(int c) const { return reinterpret_cast<uint64_t*>(keys[c ^ 1]); }
     uint64_t* own(int c) const { return reinterpret_cast<uint64_t*>(keys[c]); }
     uint32_t* ids(int c) const { return vals[c ^ 1]; }
@@ -267,13 +281,17 @@ void sort_order_items(const T* f, uint32_t n, int32_t* order, const Work& w, int
                PLMSS_KERNEL_ORDER_FIRST);
     int cur = 0;
     for (int p = 1; p < passes - 1; ++p) {
-        radix_pass(it.src(cur), it.dst(cur ^ 1), nullptr, n, workers, kRadixBits * p, false, w, info, s,
-                   kOrderKinds);
+        if (p == passes - 2)
+            radix_pass(it.src(cur), it.split_dst(cur ^ 1), nullptr, n, workers, kRadixBits * p, false, w, info, s,
+                       kOrderKinds);
+        else
+            radix_pass(it.src(cur), it.dst(cur ^ 1), nullptr, n, workers, kRadixBits * p, false, w, info, s,
+                       kOrderKinds);
         cur ^= 1;
     }
     const int last = kRadixBits * (passes - 1);
-    const auto src = it.src(cur);
-    using Src = decltype(it.src(0));
+    const auto src = it.last_src(cur);
+    using Src = decltype(it.last_src(0));
     if (inv == 0) {
         radix_pass(src, RankDst<K>{order}, nullptr, n, workers, last, false, w, info, s, kOrderKinds,
                    PLMSS_KERNEL_ORDER_INVERT);
@@ -331,7 +349,7 @@ void sort_order(const T* f, uint32_t n, int32_t* order, const Work& w, int32_t* 
     if constexpr (sizeof(K) == 4) {
         if (knob(PLMSS_TUNE_ORDER_PACKED) != 0) {
             const PackedItems it{{reinterpret_cast<uint64_t*>(w.keys[0]), reinterpret_cast<uint64_t*>(w.keys[1])},
-                                 w.vals[1]};
+                                 w.vals[1], w.npad};
             sort_order_items<T, K>(f, n, order, w, info, s, it);
             return;
         }

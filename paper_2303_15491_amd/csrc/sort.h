@@ -247,8 +247,10 @@ struct ScatterSmem {
     uint32_t tmp[kWavesPerBlock];
 };
 
+// 32-bit keys: four blocks per CU (the LDS allows four; the register budget
+// of the unrolled tile is held to it)
 template <class Src, class Dst>
-__global__ __launch_bounds__(kBlock) void k_radix_scatter(Src src, Dst dst,
+__global__ __launch_bounds__(kBlock, sizeof(typename Src::key_t) == 4 ? 4 : 2) void k_radix_scatter(Src src, Dst dst,
                                                           const uint32_t* count_ptr, uint32_t n,
                                                           int shift, const uint32_t* hist,
                                                           const uint32_t* dtotal) {
@@ -281,22 +283,23 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(Src src, Dst dst,
         // group's size to the wave's counter and gets the count before it;
         // the adds of all rows are issued back to back (LDS keeps a wave's
         // operations in order), then each group reads its leader's result
-        uint32_t local[kItems], val_tmp[kItems];
-        int leader[kItems];
+        // local[i]: the rank among the row's peers, with the group's leader
+        // lane in bits 8-13 until the leader's count is read back
+        uint32_t local[kItems], prior[kItems];
 #pragma unroll
         for (int i = 0; i < kItems; ++i) {
             const uint32_t idx = wbase + uint32_t(i) * kWave;
             const bool valid = idx < hi;
             const uint32_t d = digit_of(key[i], shift);
             const uint64_t peers = match_digit(d, valid);
-            leader[i] = peers ? top_lane(peers) : lane;
-            local[i] = uint32_t(__popcll(peers & lt));
-            uint32_t prior = 0;
-            if (valid && leader[i] == lane) prior = atomicAdd(&sm.wcnt[w][d], uint32_t(__popcll(peers)));
-            val_tmp[i] = prior;
+            const int leader = peers ? top_lane(peers) : lane;
+            local[i] = uint32_t(__popcll(peers & lt)) | (uint32_t(leader) << 8);
+            prior[i] = 0;
+            if (valid && leader == lane) prior[i] = atomicAdd(&sm.wcnt[w][d], uint32_t(__popcll(peers)));
         }
 #pragma unroll
-        for (int i = 0; i < kItems; ++i) local[i] += uint32_t(__shfl(int(val_tmp[i]), leader[i]));
+        for (int i = 0; i < kItems; ++i)
+            local[i] = (local[i] & 0xffu) + uint32_t(__shfl(int(prior[i]), int(local[i] >> 8)));
         __syncthreads();
         {
             uint32_t c[kWavesPerBlock], sum = 0;
@@ -385,21 +388,21 @@ __global__ __launch_bounds__(kBlock) void k_rank_partition(Src src, uint32_t n, 
         }
         __syncthreads();
         uint32_t local[kItems], prior[kItems];
-        int leader[kItems];
 #pragma unroll
         for (int i = 0; i < kItems; ++i) {
             const uint32_t idx = wbase + uint32_t(i) * kWave;
             const bool valid = idx < hi;
             const uint32_t d = digit_of(key[i], shift);
             const uint64_t peers = match_digit(d, valid);
-            leader[i] = peers ? top_lane(peers) : lane;
-            local[i] = uint32_t(__popcll(peers & lt));
+            const int leader = peers ? top_lane(peers) : lane;
+            local[i] = uint32_t(__popcll(peers & lt)) | (uint32_t(leader) << 8);
             prior[i] = 0;
-            if (valid && leader[i] == lane) prior[i] = atomicAdd(&wcnt[w][d], uint32_t(__popcll(peers)));
+            if (valid && leader == lane) prior[i] = atomicAdd(&wcnt[w][d], uint32_t(__popcll(peers)));
             if (valid) atomicAdd(&icount[val[i] >> id_shift], 1u);
         }
 #pragma unroll
-        for (int i = 0; i < kItems; ++i) local[i] += uint32_t(__shfl(int(prior[i]), leader[i]));
+        for (int i = 0; i < kItems; ++i)
+            local[i] = (local[i] & 0xffu) + uint32_t(__shfl(int(prior[i]), int(local[i] >> 8)));
         __syncthreads();
         {
             uint32_t c[kWavesPerBlock], sum = 0;
