@@ -853,24 +853,38 @@ template <class T>
 __global__ __launch_bounds__(kBlock) void k_ms_final(Fields F, const uint32_t* rank_of, const uint32_t* fbase) {
     uint32_t tfirst, tlast;
     block_tiles(F.dev_tiles ? gmem(F.dev_tiles)[1] : F.j_tiles, &tfirst, &tlast);
+    if (tfirst >= tlast) return;
     FieldCursor<false> cursor(F);
-    for (uint32_t tile = tfirst; tile < tlast; ++tile) {
-        const FieldDesc fd = cursor.at(F, tile);
-        const uint32_t lt = tile - fd.jbase;
-        const uint32_t base = fbase ? fbase[fd.index] : 0u;
+    // two tiles in flight: the record indices of the next tile are loaded
+    // while the ranks of the current one are gathered and stored
+    struct Stage {
+        int32_t* ms;
+        uint32_t base;
         uint32_t lv[kJPer], sl[kJPer];
         bool ok[kJPer];
+    };
+    auto load = [&](uint32_t tile, Stage& st) {
+        const FieldDesc fd = cursor.at(F, tile);
+        const uint32_t lt = tile - fd.jbase;
+        st.ms = fd.ms;
+        st.base = fbase ? fbase[fd.index] : 0u;
 #pragma unroll
         for (int i = 0; i < kJPer; ++i) {
             int x, y, z;
             jtile_xyz<T>(fd, lt, threadIdx.x + i * kBlock, &x, &y, &z);
-            ok[i] = x < fd.nx && y < fd.ny && z < fd.nz;
-            lv[i] = (uint32_t(z) * uint32_t(fd.ny) + uint32_t(y)) * uint32_t(fd.nx) + uint32_t(x);
-            sl[i] = ok[i] ? uint32_t(gmem(fd.ms)[lv[i]]) : 0u;
+            st.ok[i] = x < fd.nx && y < fd.ny && z < fd.nz;
+            st.lv[i] = (uint32_t(z) * uint32_t(fd.ny) + uint32_t(y)) * uint32_t(fd.nx) + uint32_t(x);
+            st.sl[i] = st.ok[i] ? uint32_t(gmem(fd.ms)[st.lv[i]]) : 0u;
         }
+    };
+    Stage cur, nxt;
+    load(tfirst, cur);
+    for (uint32_t tile = tfirst; tile < tlast; ++tile) {
+        if (tile + 1 < tlast) load(tile + 1, nxt);
 #pragma unroll
         for (int i = 0; i < kJPer; ++i)
-            if (ok[i]) gmem(fd.ms)[lv[i]] = int32_t(rank_of[sl[i]] - base);
+            if (cur.ok[i]) gmem(cur.ms)[cur.lv[i]] = int32_t(rank_of[cur.sl[i]] - cur.base);
+        cur = nxt;
     }
 }
 

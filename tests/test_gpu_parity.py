@@ -219,3 +219,21 @@ def test_config_3d_512_sampled(torch):
     assert (ms_s[1:] >= ms_s[:-1]).all()
     assert ms.min() == 0 and ms.max() == info[3] - 1
     assert len(np.unique(pair)) == info[3]
+
+
+def test_config_3d_512_float64_copy_is_identical(torch):
+    """The 512^3 field and its float64 copy (every value widened exactly)
+    give the same order field and labels: widening preserves the order."""
+    _say("c3-512 f64 generate")
+    f = fields.workload_c3(512)
+    _say("c3-512 f32 segment")
+    a = plmss.segment(_dev(torch, f), with_order=True)
+    torch.cuda.synchronize()
+    a = {k: v.cpu() for k, v in a.items()}
+    torch.cuda.empty_cache()
+    _say("c3-512 f64 segment")
+    b = plmss.segment(_dev(torch, f.astype(np.float64)), with_order=True)
+    torch.cuda.synchronize()
+    for k in ("asc", "desc", "ms", "order", "info"):
+        assert torch.equal(a[k], b[k].cpu()), k
+    assert int(a["info"][0]) == 0
