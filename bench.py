@@ -57,7 +57,7 @@ def algo_bytes(kind: str, invert: int):
 KIND_KNOBS = {"steepest": ("scan_depth", "scan_rounds"), "jump": ("scan_depth", "scan_rounds"),
               "ms_final": ("scan_depth", "scan_rounds")}
 for _k in ("order_first", "order_scatter", "order_last", "order_regroup", "order_invert", "order_hist"):
-    KIND_KNOBS[_k] = ("order_workers", "order_invert", "order_packed")
+    KIND_KNOBS[_k] = ("order_workers", "order_invert", "order_packed", "order_concurrent")
 for _k in ("radix_hist", "radix_scatter", "radix_digit_scan", "pair_rank"):
     KIND_KNOBS[_k] = ("sort_workers",)
 

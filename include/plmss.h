@@ -87,9 +87,14 @@ const char* plmss_build_info(void);
 
 /*
  * Full segmentation of one field (paper, Sec. "Method"): order field (only if
- * job->order != NULL), steepest neighbours, path compression, MS ids.
+ * job->order != NULL), steepest neighbours, path compression, MS ids.  The
+ * labels never depend on the materialised order field (the vertex order is
+ * also compared in place), so with an order field the two may run
+ * concurrently (PLMSS_TUNE_ORDER_CONCURRENT); the call's work is complete
+ * when `stream` reaches it either way.
  * Workspace: plmss_workspace_bytes(dims, dtype, job->order != NULL) bytes of
- * device memory, 256-byte aligned; its contents on entry do not matter.
+ * device memory, 256-byte aligned (twice as much with an order field); its
+ * contents on entry do not matter.
  * Returns PLMSS_OK, PLMSS_E_ARG, PLMSS_E_DIMS, PLMSS_E_TOO_LARGE,
  * PLMSS_E_WORKSPACE or PLMSS_E_HIP.
  */
@@ -242,6 +247,15 @@ const char* plmss_kernel_name(int32_t kind);
  *                              their ids in one 64-bit word until the last
  *                              pass, which reads them as two arrays; 0 = two
  *                              arrays throughout.
+ *   PLMSS_TUNE_ORDER_CONCURRENT  plmss_segment with an order field: 1 = the
+ *                              order field is built on a
+ *                              library-owned stream (one per device,
+ *                              non-blocking, default priority, kept for the
+ *                              life of the process) that waits for the
+ *                              caller's stream, while the labels run on the
+ *                              caller's stream, which then waits for the order
+ *                              field; 0 (default) = everything on the caller's
+ *                              stream, so that each kernel's time is its own.
  *   PLMSS_TUNE_SCAN_ROUNDS     in-tile path-compression sweeps of the
  *                              neighbour scan (1..8, default 3); what they
  *                              leave unfinished the cross-tile chase follows.
@@ -266,7 +280,8 @@ const char* plmss_kernel_name(int32_t kind);
 #define PLMSS_TUNE_SCAN_DEPTH 4
 #define PLMSS_TUNE_ORDER_PACKED 5
 #define PLMSS_TUNE_SCAN_ROUNDS 6
-#define PLMSS_TUNE_KNOBS 7
+#define PLMSS_TUNE_ORDER_CONCURRENT 7
+#define PLMSS_TUNE_KNOBS 8
 int32_t plmss_tune_set(int32_t knob, int64_t value);
 int64_t plmss_tune_get(int32_t knob);
 

@@ -32,6 +32,7 @@ SPACE = {
     "order_invert": [1, 0, 2, 4],
     "order_packed": [1, 0],
     "scan_rounds": [3, 2, 4],
+    "order_concurrent": [0, 1],  # not tuned by default: overlapping streams blur per-kernel times
     "sort_workers": [512, 256, 1024, 2048, 4096],
     "scan_depth": [8, 16, 32],
     "persist_blocks": [512, 1024, 2048, 4096, 8192, 16384],

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cstdint>
+#include <mutex>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -33,10 +34,11 @@ constexpr KnobRange kKnobs[PLMSS_TUNE_KNOBS] = {
     {8, 32, 16, false, true},                  // SCAN_DEPTH: 8, 16 or 32 planes
     {1, 1, 1, true, false},                    // ORDER_PACKED: 32-bit keys packed with ids
     {1, 8, kResolveRounds, false, false},      // SCAN_ROUNDS: in-tile jumping sweeps
+    {1, 1, 0, true, false},                    // ORDER_CONCURRENT: order field on a second stream
 };
 std::atomic<int64_t> g_knob[PLMSS_TUNE_KNOBS] = {kKnobs[0].def, kKnobs[1].def, kKnobs[2].def,
                                                  kKnobs[3].def, kKnobs[4].def, kKnobs[5].def,
-                                                 kKnobs[6].def};
+                                                 kKnobs[6].def, kKnobs[7].def};
 
 int64_t knob(int k) { return g_knob[k].load(std::memory_order_relaxed); }
 unsigned sort_workers() { return unsigned(knob(PLMSS_TUNE_SORT_WORKERS)); }
@@ -477,15 +479,17 @@ void ms_from_pairs(const LaunchSet& L, const Work& w, hipStream_t s) {
         if (L.used[c]) launch_ms_final_cls(c, L.cls[c], L.grid_j[c], w, s);
 }
 
-// The segmentation of every field of L (an order field only for a single
-// field: `order` != nullptr).
-void run_set(const LaunchSet& L, const void* field, int32_t* order, uint32_t n_single, const Work& w,
-             hipStream_t s) {
-    uint32_t* U = reinterpret_cast<uint32_t*>(w.keys[0]);
-    uint32_t* D = U + w.npad;
+void init_set(const LaunchSet& L, const Work& w, hipStream_t s) {
     launch(PLMSS_KERNEL_MISC, s, [&] { k_init<<<1, 64, 0, s>>>(nullptr, w.counters, 8); });
     launch(PLMSS_KERNEL_MISC, s, [&] { k_init_fields<<<L.capacity ? 64u : 1u, kBlock, 0, s>>>(L.all); });
-    if (order) order_any(field, L.dtype, n_single, order, w, L.all.one.info, s);
+}
+
+// Steepest neighbours, chase, MS ids for every field of L; the vertex order
+// comes from a materialised order field when `order` is given, else from the
+// field values.
+void labels_set(const LaunchSet& L, const int32_t* order, const Work& w, hipStream_t s) {
+    uint32_t* U = reinterpret_cast<uint32_t*>(w.keys[0]);
+    uint32_t* D = U + w.npad;
     for (int c = 0; c < kClasses; ++c)
         if (L.used[c]) {
             Fields F = L.cls[c];
@@ -495,6 +499,59 @@ void run_set(const LaunchSet& L, const void* field, int32_t* order, uint32_t n_s
     for (int c = 0; c < kClasses; ++c)
         if (L.used[c]) launch_chase_cls<true>(c, L.cls[c], L.grid_j[c], U, D, L.bn, w, s);
     ms_from_pairs(L, w, s);
+}
+
+// The segmentation of every field of L (an order field only for a single
+// field: `order` != nullptr), all on stream s.
+void run_set(const LaunchSet& L, const void* field, int32_t* order, uint32_t n_single, const Work& w,
+             hipStream_t s) {
+    init_set(L, w, s);
+    if (order) order_any(field, L.dtype, n_single, order, w, L.all.one.info, s);
+    labels_set(L, order, w, s);
+}
+
+// A library-owned non-blocking stream per device (created on first use, kept
+// for the life of the process), default priority.
+hipStream_t aux_stream() {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mutex;
+    static hipStream_t streams[kMaxDevices] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(mutex);
+    if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess) {
+        streams[dev] = nullptr;
+        return nullptr;
+    }
+    return streams[dev];
+}
+
+// One field with its order field: the order field is sorted on the auxiliary
+// stream (its own half of the workspace, wo) while the labels, which compare
+// the field values in place and so do not need it, run on s; s then waits for
+// the order field.  Same results as run_set.
+int run_single_concurrent(const LaunchSet& L, const plmss_job& job, uint32_t n, const Work& w, const Work& wo,
+                          hipStream_t s) {
+    hipStream_t aux = aux_stream();
+    if (!aux) return PLMSS_E_HIP;
+    hipEvent_t fork = nullptr, join = nullptr;
+    if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) return PLMSS_E_HIP;
+    if (hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess) {
+        (void)hipEventDestroy(fork);
+        return PLMSS_E_HIP;
+    }
+    init_set(L, w, s);  // clears info before either stream may report into it
+    int rc = PLMSS_OK;
+    if (hipEventRecord(fork, s) != hipSuccess || hipStreamWaitEvent(aux, fork, 0) != hipSuccess) rc = PLMSS_E_HIP;
+    if (rc == PLMSS_OK) {
+        order_any(job.field, L.dtype, n, job.order, wo, L.all.one.info, aux);
+        if (hipEventRecord(join, aux) != hipSuccess) rc = PLMSS_E_HIP;
+    }
+    labels_set(L, nullptr, w, s);
+    if (rc == PLMSS_OK && hipStreamWaitEvent(s, join, 0) != hipSuccess) rc = PLMSS_E_HIP;
+    (void)hipEventDestroy(fork);  // released once the recorded work completes
+    (void)hipEventDestroy(join);
+    return rc;
 }
 
 FieldDesc desc_of(const plmss_job& j, uint32_t vbase, uint32_t sbase, uint32_t jbase, uint32_t index = 0) {
@@ -696,8 +753,9 @@ size_t plmss_workspace_bytes(plmss_dims dims, int32_t dtype, int32_t with_order)
     uint64_t n;
     if (check_dims(dims, &n) != PLMSS_OK) return 0;
     (void)dtype;
-    (void)with_order;
-    return work_sizes(n, 1, 0).total;
+    // with the order field: a second half for the order sort, which may run
+    // concurrently with the labels
+    return work_sizes(n, 1, 0).total * (with_order ? 2 : 1);
 }
 
 int plmss_segment(const plmss_job* job, void* workspace, size_t workspace_bytes, void* stream) {
@@ -707,10 +765,15 @@ int plmss_segment(const plmss_job* job, void* workspace, size_t workspace_bytes,
     int rc = check_dims(job->dims, &n);
     if (rc) return rc;
     const Sizes sz = work_sizes(n, 1, 0);
-    if (!ws_ok(workspace, workspace_bytes, sz.total)) return PLMSS_E_WORKSPACE;
+    if (!ws_ok(workspace, workspace_bytes, sz.total * (job->order ? 2 : 1))) return PLMSS_E_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const Work w = carve(workspace, sz);
     const LaunchSet L = single_set(*job, n, scan_depth());
+    if (job->order && knob(PLMSS_TUNE_ORDER_CONCURRENT) != 0) {
+        const Work wo = carve(static_cast<uint8_t*>(workspace) + sz.total, sz);
+        const int rc = run_single_concurrent(L, *job, uint32_t(n), w, wo, s);
+        return rc != PLMSS_OK ? rc : launch_status();
+    }
     run_set(L, job->field, job->order, uint32_t(n), w, s);
     return launch_status();
 }

@@ -84,7 +84,9 @@ def test_workspace_sizes():
     small = lib.plmss_workspace_bytes(plmss.Dims(64, 64, 1), plmss.F32, 0)
     big = lib.plmss_workspace_bytes(plmss.Dims(512, 512, 512), plmss.F32, 1)
     assert 0 < small < big
-    assert big < 40 * 512**3  # about 28 bytes per vertex plus fixed tables
+    assert big < 64 * 512**3  # about 28 bytes per vertex, twice with an order field, plus tables
+    labels_only = lib.plmss_workspace_bytes(plmss.Dims(512, 512, 512), plmss.F32, 0)
+    assert labels_only < 32 * 512**3 and big == 2 * labels_only
     assert lib.plmss_workspace_bytes(plmss.Dims(0, 1, 1), plmss.F32, 0) == 0
     assert lib.plmss_ms_workspace_bytes(0) == 0
 
@@ -111,9 +113,10 @@ def test_tuning_knobs_validate_ranges():
         assert lib.plmss_tune_set(plmss.KNOBS["order_invert"], 65) == plmss.E_ARG
         assert lib.plmss_tune_set(plmss.KNOBS["scan_rounds"], 0) == plmss.E_ARG
         plmss.tune_set(order_workers=0, order_invert=0, sort_workers=512, persist_blocks=4096, scan_depth=8,
-                       order_packed=1, scan_rounds=1)
+                       order_packed=1, scan_rounds=1, order_concurrent=0)
         assert plmss.tune_get() == {"order_workers": 0, "order_invert": 0, "sort_workers": 512,
-                                    "persist_blocks": 4096, "scan_depth": 8, "order_packed": 1, "scan_rounds": 1}
+                                    "persist_blocks": 4096, "scan_depth": 8, "order_packed": 1, "scan_rounds": 1,
+                                    "order_concurrent": 0}
         with pytest.raises(plmss.PlmssError):
             plmss.tune_set(order_workers=10)
         with pytest.raises(KeyError):
