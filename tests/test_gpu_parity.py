@@ -91,7 +91,7 @@ def test_ragged_tiles_both_paths(torch, shape):
     {"order_packed": 0, "order_invert": 64, "order_workers": 0},
     {"sort_workers": 64}, {"sort_workers": 4096},
     {"scan_rounds": 1}, {"scan_rounds": 8, "scan_depth": 32}, {"scan_rounds": 2, "scan_depth": 8},
-    {"order_concurrent": 0}, {"order_concurrent": 0, "order_packed": 0},
+    {"order_concurrent": 1}, {"order_concurrent": 1, "order_packed": 0},
 ])
 def test_launch_shapes_keep_results(torch, knobs):
     """Every launch-shape knob setting gives the oracle's labels (tile depths
