@@ -51,6 +51,12 @@ __device__ __forceinline__ uint64_t sos_key(double f) {
     u = (u == 0x8000000000000000ull) ? 0ull : u;
     return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
 }
+// NaN from the key alone: the transform maps +NaNs above key(+inf) and -NaNs
+// below key(-inf), and nothing else lies there.
+__device__ __forceinline__ bool key_is_nan(uint32_t k) { return k > 0xFF800000u || k < 0x007FFFFFu; }
+__device__ __forceinline__ bool key_is_nan(uint64_t k) {
+    return k > 0xFFF0000000000000ull || k < 0x000FFFFFFFFFFFFFull;
+}
 __device__ __forceinline__ bool is_nan(float f) {
     return (__float_as_uint(f) & 0x7fffffffu) > 0x7f800000u;
 }

@@ -328,16 +328,19 @@ __global__ __launch_bounds__(kBlock) void k_steepest(Fields F, uint32_t* up, uin
     if (t < 16) off_tab[t] = t < 15 ? code_offset(t, g.nx, S) : 0;
     // this thread's share of a plane load: LDS slot and in-plane offset, the
     // same for every plane
+    // Slots outside the grid read the plane's first vertex and store a zero
+    // key instead, so a plane's loads need no branch and issue together.
     int ld_slot[kLoads];
-    int64_t ld_off[kLoads];
+    bool ld_in[kLoads];
+    uint32_t ld_off[kLoads];
 #pragma unroll
     for (int k = 0; k < kLoads; ++k) {
         const int i = t + k * kBlock;
         const int r = i / PX, c = i - r * PX;
         const int gx = x0 - 1 + c, gy = y0 - 1 + r;
-        const bool in = i < PY * PX && gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny;
+        ld_in[k] = i < PY * PX && gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny;
         ld_slot[k] = i < PY * PX ? i : -1;
-        ld_off[k] = in ? int64_t(gy) * int64_t(sx) + gx : -1;
+        ld_off[k] = ld_in[k] ? uint32_t(gy) * uint32_t(sx) + uint32_t(gx) : 0u;
     }
     bool nan = false;
     // plane loads go through registers as raw values, so that the next
@@ -348,13 +351,13 @@ __global__ __launch_bounds__(kBlock) void k_steepest(Fields F, uint32_t* up, uin
     auto fetch_plane = [&](int z) {
         const size_t zb = size_t(z) * sxy;
 #pragma unroll
-        for (int k = 0; k < kLoads; ++k) pre[k] = ld_off[k] >= 0 ? src.fetch(zb + size_t(ld_off[k])) : R(0);
+        for (int k = 0; k < kLoads; ++k) pre[k] = src.fetch(zb + size_t(ld_off[k]));
     };
     auto store_plane = [&](int slot) {
         K* dst = &pl[kSquares ? 0 : slot][0][0];
 #pragma unroll
         for (int k = 0; k < kLoads; ++k)
-            if (ld_slot[k] >= 0) dst[ld_slot[k]] = ld_off[k] >= 0 ? Src::key(pre[k], nan) : K(0);
+            if (ld_slot[k] >= 0) dst[ld_slot[k]] = ld_in[k] ? Src::key(pre[k], nan) : K(0);
     };
     auto load_plane = [&](int slot, int z) {
         fetch_plane(z);
@@ -652,13 +655,20 @@ __global__ __launch_bounds__(kBlock) void k_chase(Fields F, uint32_t* U, uint32_
             jtile_xyz<T>(fd, lt, t + i * kBlock, &x, &y, &z);
             ok[i] = x < fd.nx && y < fd.ny && z < fd.nz;
             lv[i] = ok[i] ? (uint32_t(z) * uint32_t(fd.ny) + uint32_t(y)) * uint32_t(fd.nx) + uint32_t(x) : 0u;
+            // lanes past the field's edge read its vertex 0 (lv = 0) and drop
+            // the value, so the loads need no branch and issue together
             if (CHASE) {
-                pu[i] = ok[i] ? U[fd.vbase + lv[i]] : kMark;
-                pd[i] = ok[i] ? D[fd.vbase + lv[i]] : kMark;
+                pu[i] = gmem(U)[fd.vbase + lv[i]];
+                pd[i] = gmem(D)[fd.vbase + lv[i]];
             } else {
-                pu[i] = ok[i] ? uint32_t(gmem(fd.desc)[lv[i]]) + fd.vbase : 0u;
-                pd[i] = ok[i] ? uint32_t(gmem(fd.asc)[lv[i]]) + fd.vbase : 0u;
+                pu[i] = uint32_t(gmem(fd.desc)[lv[i]]) + fd.vbase;
+                pd[i] = uint32_t(gmem(fd.asc)[lv[i]]) + fd.vbase;
             }
+        }
+#pragma unroll
+        for (int i = 0; i < kJPer; ++i) {
+            pu[i] = ok[i] ? pu[i] : (CHASE ? kMark : 0u);
+            pd[i] = ok[i] ? pd[i] : (CHASE ? kMark : 0u);
         }
         if (CHASE) {
             // the eight vertices of a thread advance together, so their
@@ -667,19 +677,29 @@ __global__ __launch_bounds__(kBlock) void k_chase(Fields F, uint32_t* U, uint32_
             bool pending = true;
             uint32_t hops = 0;
             while (pending && hops < kMaxHops) {
+                // all gathers of the hop first, then the write-backs, so that
+                // no store waits on its own load before the next is issued
+                uint32_t nu[kJPer], nd[kJPer];
+#pragma unroll
+                for (int i = 0; i < kJPer; ++i) {
+                    nu[i] = pu[i];
+                    nd[i] = pd[i];
+                    if (!(pu[i] & kMark)) nu[i] = gmem(U)[pu[i]];
+                    if (!(pd[i] & kMark)) nd[i] = gmem(D)[pd[i]];
+                }
                 pending = false;
 #pragma unroll
                 for (int i = 0; i < kJPer; ++i) {
                     if (!(pu[i] & kMark)) {
-                        pu[i] = U[pu[i]];
-                        if (hops) U[fd.vbase + lv[i]] = pu[i];
+                        if (hops) gmem(U)[fd.vbase + lv[i]] = nu[i];
                         pending = true;
                     }
                     if (!(pd[i] & kMark)) {
-                        pd[i] = D[pd[i]];
-                        if (hops) D[fd.vbase + lv[i]] = pd[i];
+                        if (hops) gmem(D)[fd.vbase + lv[i]] = nd[i];
                         pending = true;
                     }
+                    pu[i] = nu[i];
+                    pd[i] = nd[i];
                 }
                 ++hops;
             }
@@ -795,10 +815,9 @@ __global__ __launch_bounds__(kBlock) void k_jump(int32_t* desc, int32_t* asc, ui
 // ---- pair ranking ---------------------------------------------------------------------
 
 // flag[i] = (i == 0 || key[i] != key[i-1]); rank[i] = (flags in 0..i) - 1.
-__device__ __forceinline__ uint32_t pair_flag(const uint64_t* keys, uint32_t i) {
-    return (i == 0 || keys[i] != keys[i - 1]) ? 1u : 0u;
-}
-
+// Both kernels read from indices clamped into the slice, so every load of a
+// tile is issued before the first is waited for; items past the slice are
+// masked afterwards.
 __global__ __launch_bounds__(kBlock) void k_rank_reduce(const uint64_t* keys,
                                                         const uint32_t* count_ptr,
                                                         uint32_t* partial) {
@@ -807,10 +826,17 @@ __global__ __launch_bounds__(kBlock) void k_rank_reduce(const uint64_t* keys,
     worker_range(*count_ptr, blockIdx.x, gridDim.x, kTile, &lo, &hi);
     uint32_t s = 0;
     for (uint32_t tile = lo; tile < hi; tile += kTile) {
+        uint64_t k[kItems], p[kItems];
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            const uint32_t idx = min(tile + uint32_t(i) * kBlock + threadIdx.x, hi - 1u);
+            k[i] = keys[idx];
+            p[i] = keys[idx ? idx - 1u : 0u];
+        }
 #pragma unroll
         for (int i = 0; i < kItems; ++i) {
             const uint32_t idx = tile + uint32_t(i) * kBlock + threadIdx.x;
-            if (idx < hi) s += pair_flag(keys, idx);
+            if (idx < hi) s += (idx == 0 || k[i] != p[i]) ? 1u : 0u;
         }
     }
     uint32_t tot;
@@ -818,7 +844,7 @@ __global__ __launch_bounds__(kBlock) void k_rank_reduce(const uint64_t* keys,
     if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
-// rank_of_slot[vals[i]] = rank[i].
+// rank_of_slot[vals[i]] = rank[i]; each thread ranks kItems consecutive items.
 __global__ __launch_bounds__(kBlock) void k_rank_apply(const uint64_t* keys, const uint32_t* vals,
                                                        const uint32_t* count_ptr,
                                                        const uint32_t* partial,
@@ -829,10 +855,20 @@ __global__ __launch_bounds__(kBlock) void k_rank_apply(const uint64_t* keys, con
     uint32_t run = partial[blockIdx.x];
     for (uint32_t tile = lo; tile < hi; tile += kTile) {
         const uint32_t beg = tile + threadIdx.x * kItems;
+        uint64_t k[kItems];
+        uint32_t v[kItems];
+        const uint64_t before = keys[beg ? min(beg, hi) - 1u : 0u];
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            const uint32_t idx = min(beg + uint32_t(i), hi - 1u);
+            k[i] = keys[idx];
+            v[i] = vals[idx];
+        }
         uint32_t f[kItems], s = 0;
 #pragma unroll
         for (int i = 0; i < kItems; ++i) {
-            f[i] = beg + i < hi ? pair_flag(keys, beg + i) : 0u;
+            const uint64_t prev = i ? k[i - 1] : before;
+            f[i] = (beg + i < hi && (beg + i == 0 || k[i] != prev)) ? 1u : 0u;
             s += f[i];
         }
         uint32_t tot;
@@ -840,7 +876,7 @@ __global__ __launch_bounds__(kBlock) void k_rank_apply(const uint64_t* keys, con
 #pragma unroll
         for (int i = 0; i < kItems; ++i) {
             r += f[i];
-            if (beg + i < hi) rank_of_slot[vals[beg + i]] = r - 1;
+            if (beg + i < hi) rank_of_slot[v[i]] = r - 1;
         }
         run += tot;
     }
@@ -874,16 +910,21 @@ __global__ __launch_bounds__(kBlock) void k_ms_final(Fields F, const uint32_t* r
             jtile_xyz<T>(fd, lt, threadIdx.x + i * kBlock, &x, &y, &z);
             st.ok[i] = x < fd.nx && y < fd.ny && z < fd.nz;
             st.lv[i] = (uint32_t(z) * uint32_t(fd.ny) + uint32_t(y)) * uint32_t(fd.nx) + uint32_t(x);
-            st.sl[i] = st.ok[i] ? uint32_t(gmem(fd.ms)[st.lv[i]]) : 0u;
+            // vertex 0 of the field stands in for lanes past its edge, so the
+            // loads need no branch and issue together
+            st.sl[i] = uint32_t(gmem(fd.ms)[st.ok[i] ? st.lv[i] : 0u]);
         }
     };
     Stage cur, nxt;
     load(tfirst, cur);
     for (uint32_t tile = tfirst; tile < tlast; ++tile) {
         if (tile + 1 < tlast) load(tile + 1, nxt);
+        uint32_t r[kJPer];
+#pragma unroll
+        for (int i = 0; i < kJPer; ++i) r[i] = gmem(rank_of)[cur.ok[i] ? cur.sl[i] : 0u];
 #pragma unroll
         for (int i = 0; i < kJPer; ++i)
-            if (cur.ok[i]) gmem(cur.ms)[cur.lv[i]] = int32_t(rank_of[cur.sl[i]] - cur.base);
+            if (cur.ok[i]) gmem(cur.ms)[cur.lv[i]] = int32_t(r[i] - cur.base);
         cur = nxt;
     }
 }

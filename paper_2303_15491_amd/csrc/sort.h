@@ -47,7 +47,8 @@ struct FieldSrc {
     const T* f;
     __device__ __forceinline__ K key(uint32_t i) const { return sos_key(f[i]); }
     __device__ __forceinline__ uint32_t val(uint32_t i) const { return i; }
-    __device__ __forceinline__ bool nan(uint32_t i) const { return is_nan(f[i]); }
+    // NaN test on the transformed key, so the value is loaded once
+    __device__ __forceinline__ static bool nan_key(K k) { return key_is_nan(k); }
 };
 
 template <typename K>
@@ -57,7 +58,7 @@ struct ArraySrc {
     const uint32_t* vals;
     __device__ __forceinline__ K key(uint32_t i) const { return keys[i]; }
     __device__ __forceinline__ uint32_t val(uint32_t i) const { return vals[i]; }
-    __device__ __forceinline__ bool nan(uint32_t) const { return false; }
+    __device__ __forceinline__ static bool nan_key(key_t) { return false; }
 };
 
 // 32-bit keys and their ids packed in one word, key in the high half: one
@@ -67,7 +68,7 @@ struct PackedSrc {
     const uint64_t* kv;
     __device__ __forceinline__ uint32_t key(uint32_t i) const { return uint32_t(kv[i] >> 32); }
     __device__ __forceinline__ uint32_t val(uint32_t i) const { return uint32_t(kv[i]); }
-    __device__ __forceinline__ bool nan(uint32_t) const { return false; }
+    __device__ __forceinline__ static bool nan_key(key_t) { return false; }
 };
 
 struct PackedDst {
@@ -172,21 +173,20 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(Src src, const uint32_t* 
     for (uint32_t tile = lo; tile < hi; tile += kTile) {
         K key[kItems];
         uint32_t val[kItems];
+        // every load reads a valid element (the index is clamped to the
+        // slice), so all of them are issued before the first is waited for;
+        // items past the slice are masked afterwards
 #pragma unroll
         for (int i = 0; i < kItems; ++i) {
-            const uint32_t idx = tile + uint32_t(i) * kBlock + t;
-            if (IDS) {
-                if (idx < hi) {
-                    load_item(src, idx, key[i], val[i]);
-                } else {
-                    key[i] = K(0);
-                    val[i] = 0u;
-                }
-            } else {
-                key[i] = idx < hi ? src.key(idx) : K(0);
-            }
-            if (CHECK_NAN && idx < hi) bad |= src.nan(idx);
+            const uint32_t idx = min(tile + uint32_t(i) * kBlock + t, hi - 1u);
+            if (IDS)
+                load_item(src, idx, key[i], val[i]);
+            else
+                key[i] = src.key(idx);
         }
+#pragma unroll
+        for (int i = 0; i < kItems; ++i)
+            if (CHECK_NAN && tile + uint32_t(i) * kBlock + t < hi) bad |= Src::nan_key(key[i]);
 #pragma unroll
         for (int i = 0; i < kItems; ++i) {
             const uint32_t idx = tile + uint32_t(i) * kBlock + t;
@@ -272,12 +272,9 @@ __global__ __launch_bounds__(kBlock, sizeof(typename Src::key_t) == 4 ? 4 : 2) v
         K key[kItems];
         uint32_t val[kItems];
         const uint32_t wbase = tile + uint32_t(w) * kWave * kItems + lane;
+        // clamped indices: all loads issue before the first wait
 #pragma unroll
-        for (int i = 0; i < kItems; ++i) {
-            const uint32_t idx = wbase + uint32_t(i) * kWave;
-            key[i] = idx < hi ? src.key(idx) : K(0);
-            val[i] = idx < hi ? src.val(idx) : 0u;
-        }
+        for (int i = 0; i < kItems; ++i) load_item(src, min(wbase + uint32_t(i) * kWave, hi - 1u), key[i], val[i]);
         __syncthreads();
         // rank inside the wave: the highest lane of each digit group adds the
         // group's size to the wave's counter and gets the count before it;
@@ -377,15 +374,7 @@ __global__ __launch_bounds__(kBlock) void k_rank_partition(Src src, uint32_t n, 
         uint32_t val[kItems];
         const uint32_t wbase = tile + uint32_t(w) * kWave * kItems + lane;
 #pragma unroll
-        for (int i = 0; i < kItems; ++i) {
-            const uint32_t idx = wbase + uint32_t(i) * kWave;
-            if (idx < hi) {
-                load_item(src, idx, key[i], val[i]);
-            } else {
-                key[i] = K(0);
-                val[i] = 0u;
-            }
-        }
+        for (int i = 0; i < kItems; ++i) load_item(src, min(wbase + uint32_t(i) * kWave, hi - 1u), key[i], val[i]);
         __syncthreads();
         uint32_t local[kItems], prior[kItems];
 #pragma unroll
@@ -488,9 +477,10 @@ __global__ __launch_bounds__(kBlock) void k_chunk_partition(const uint64_t* part
     uint64_t x[kItems];
     uint32_t rel[kItems];
 #pragma unroll
+    for (int i = 0; i < kItems; ++i) x[i] = parts[min(lo + uint32_t(i) * kBlock + t, hi - 1u)];
+#pragma unroll
     for (int i = 0; i < kItems; ++i) {
         const uint32_t j = lo + uint32_t(i) * kBlock + t;
-        x[i] = j < hi ? parts[j] : 0ull;
         rel[i] = j < hi ? (uint32_t(x[i] >> 32) >> kChunkBits) - first : uint32_t(kMaxRel);
         if (rel[i] < uint32_t(kMaxRel)) atomicAdd(&cnt[rel[i]], 1u);
     }
