@@ -499,20 +499,45 @@ __global__ __launch_bounds__(kBlock) void k_steepest(Fields F, uint32_t* up, uin
         // pointer.  Planes past the field's last plane hold nothing of this
         // tile and are skipped; every pointer written above stays in the
         // planes that were written.
-        auto step = [&](int e, bool& ch) {
-            if (e / RPW >= nz_t) return;
-            const int li = li0 + (e / RPW) * (TY * kTX) + (e % RPW) * kTX;
-            const uint32_t own = lp[li];
-            const uint32_t qu = lp[own & (kExit - 1)], qd = lp[(own >> 16) & (kExit - 1)];
-            const uint32_t q = (qu & 0xffffu) | (qd & 0xffff0000u);
-            const uint32_t cross = own | q, diff = own ^ q;
-            const bool su = (cross & kExit) || (diff & 0xffffu) == 0u;
-            const bool sd = (cross & (kExit << 16)) || (diff >> 16) == 0u;
-            const uint32_t keep = (su ? 0x0000ffffu : 0u) | (sd ? 0xffff0000u : 0u);
-            const uint32_t nw = (own & keep) | (q & ~keep);
-            if (nw != own) {
-                lp[li] = nw;  // each entry has one owner
-                ch = true;
+        // Entries are taken kGroup at a time: the group's own pointers are
+        // read, then their targets, then the changed entries are written, so
+        // that the LDS reads of a group are in flight together instead of each
+        // waiting for the write before it.  Inside a group a target may be
+        // read before its own update; any pointer on the path is a valid
+        // value, so this only changes how much each sweep compresses.
+        constexpr int kGroup = 4;
+        static_assert(kMine % kGroup == 0, "whole groups");
+        auto group = [&](int g0, bool rev, bool& ch) {
+            if (g0 / RPW >= nz_t) return;
+            int li[kGroup];
+            bool act[kGroup];
+            uint32_t own[kGroup], q[kGroup];
+#pragma unroll
+            for (int k = 0; k < kGroup; ++k) {
+                const int e = rev ? g0 + (kGroup - 1 - k) : g0 + k;
+                act[k] = e / RPW < nz_t;
+                li[k] = li0 + (e / RPW) * (TY * kTX) + (e % RPW) * kTX;
+                own[k] = lp[li[k]];
+            }
+#pragma unroll
+            for (int k = 0; k < kGroup; ++k) {
+                // an entry in a plane past the field reads itself (in bounds)
+                // and is not written
+                own[k] = act[k] ? own[k] : (uint32_t(li[k]) | (uint32_t(li[k]) << 16));
+                const uint32_t qu = lp[own[k] & (kExit - 1)], qd = lp[(own[k] >> 16) & (kExit - 1)];
+                q[k] = (qu & 0xffffu) | (qd & 0xffff0000u);
+            }
+#pragma unroll
+            for (int k = 0; k < kGroup; ++k) {
+                const uint32_t cross = own[k] | q[k], diff = own[k] ^ q[k];
+                const bool su = (cross & kExit) || (diff & 0xffffu) == 0u;
+                const bool sd = (cross & (kExit << 16)) || (diff >> 16) == 0u;
+                const uint32_t keep = (su ? 0x0000ffffu : 0u) | (sd ? 0xffff0000u : 0u);
+                const uint32_t nw = (own[k] & keep) | (q[k] & ~keep);
+                if (act[k] && nw != own[k]) {
+                    lp[li[k]] = nw;  // each entry has one owner
+                    ch = true;
+                }
             }
         };
         // sweeps alternate direction, so chains of either orientation compress
@@ -523,10 +548,10 @@ __global__ __launch_bounds__(kBlock) void k_steepest(Fields F, uint32_t* up, uin
             bool ch = false;
             if (round & 1) {
 #pragma unroll
-                for (int e = kMine - 1; e >= 0; --e) step(e, ch);
+                for (int g = kMine - kGroup; g >= 0; g -= kGroup) group(g, true, ch);
             } else {
 #pragma unroll
-                for (int e = 0; e < kMine; ++e) step(e, ch);
+                for (int g = 0; g < kMine; g += kGroup) group(g, false, ch);
             }
             if (!__syncthreads_or(ch)) break;
         }

@@ -131,15 +131,20 @@ __device__ __forceinline__ uint32_t digit_of(K k, int shift) {
 }
 
 // Lanes of the wave whose digit equals this lane's (only lanes with valid set).
+// Per bit: s = all ones where this lane's bit is set, m = the wave's ballot of
+// that bit; a lane keeps the lanes where m agrees with s, ~(m ^ s), one
+// three-input bit operation per 32-bit half.
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
-    uint64_t peers = __ballot(valid);
+    const uint64_t v = __ballot(valid);
+    uint32_t lo = uint32_t(v), hi = uint32_t(v >> 32);
 #pragma unroll
     for (int b = 0; b < kRadixBits; ++b) {
-        const bool bit = (d >> b) & 1u;
-        const uint64_t m = __ballot(bit);
-        peers &= bit ? m : ~m;
+        const uint32_t s = uint32_t(int32_t(d << (31 - b)) >> 31);
+        const uint64_t m = __ballot(s != 0u);
+        lo &= ~(uint32_t(m) ^ s);
+        hi &= ~(uint32_t(m >> 32) ^ s);
     }
-    return peers;
+    return (uint64_t(hi) << 32) | lo;
 }
 
 // Highest lane of a non-empty lane set.
