@@ -229,10 +229,10 @@ const char* plmss_kernel_name(int32_t kind);
  * Launch-shape knobs, for the autotuner.  Process-wide; a call reads them when
  * it enqueues its kernels (a plan's hipGraph keeps the values it was captured
  * with).  Results never depend on them, only speed does.
- *   PLMSS_TUNE_ORDER_WORKERS   blocks of each order-field radix pass: 0 = one
- *                              per 4096-key tile, or 64..65536 (default
- *                              8192), each block then owning a contiguous run
- *                              of tiles.
+ *   PLMSS_TUNE_ORDER_WORKERS   blocks of each order-field radix pass: 0
+ *                              (default) = one per 4096-key tile, or
+ *                              64..65536, each block then owning a contiguous
+ *                              run of tiles.
  *   PLMSS_TUNE_ORDER_INVERT    how order[id] = position is written: 0 = by the
  *                              last radix pass itself (scattered writes over
  *                              the whole array); 1 (default) = the last pass

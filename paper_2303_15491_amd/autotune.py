@@ -28,7 +28,7 @@ import threading
 from . import KNOBS, Plan, PlmssError, batch_needs, segment, tune_get, tune_set
 
 SPACE = {
-    "order_workers": [8192, 4096, 16384, 0],
+    "order_workers": [0, 8192, 16384, 4096],
     "order_invert": [1, 0, 2, 4],
     "order_packed": [1, 0],
     "scan_rounds": [3, 2, 4],

@@ -27,7 +27,7 @@ struct KnobRange {
     bool zero_ok, pow2;
 };
 constexpr KnobRange kKnobs[PLMSS_TUNE_KNOBS] = {
-    {64, 1 << 16, 8192, true, false},          // ORDER_WORKERS: 0 = one block per tile
+    {64, 1 << 16, 0, true, false},             // ORDER_WORKERS: 0 = one block per tile
     {1, 64, 1, true, false},                   // ORDER_INVERT: 0 fused, 1 id ranges, 2.. windows
     {64, kMaxWorkers, kWorkers, false, false},  // SORT_WORKERS
     {64, 16384, 2048, false, false},           // PERSIST_BLOCKS
@@ -199,12 +199,28 @@ void launch(int kind, hipStream_t s, F&& f) {
 
 // ---- radix sort driver -------------------------------------------------------------------
 
-// Trace kinds of one radix pass: histogram, digit scan, scatter.
+// Trace kinds of one radix pass: histogram and scatter.
 struct PassKinds {
-    int hist, scan, scatter;
+    int hist, scatter;  // the digit scans are PLMSS_KERNEL_RADIX_SCAN
 };
-constexpr PassKinds kPairKinds{PLMSS_KERNEL_RADIX_HIST, PLMSS_KERNEL_RADIX_SCAN, PLMSS_KERNEL_RADIX_SCATTER};
-constexpr PassKinds kOrderKinds{PLMSS_KERNEL_ORDER_HIST, PLMSS_KERNEL_RADIX_SCAN, PLMSS_KERNEL_ORDER_SCATTER};
+constexpr PassKinds kPairKinds{PLMSS_KERNEL_RADIX_HIST, PLMSS_KERNEL_RADIX_SCATTER};
+constexpr PassKinds kOrderKinds{PLMSS_KERNEL_ORDER_HIST, PLMSS_KERNEL_ORDER_SCATTER};
+static_assert(kRadix * kMaxSegments <= kMaxWorkers, "segment sums fit the partial buffer");
+
+// Exclusive scan of the kRadix rows of `workers` entries in hist (row sums in
+// dtotal), segmented over several blocks per row when rows are long; the
+// segment sums go to w.partial.
+void digit_scan(uint32_t* hist, uint32_t* dtotal, unsigned workers, const Work& w, hipStream_t s) {
+    const int nseg = int(std::min<unsigned>(kMaxSegments, (workers + kSegment - 1) / kSegment));
+    const int seglen = int((workers + unsigned(nseg) - 1) / unsigned(nseg));
+    if (nseg > 1)
+        launch(PLMSS_KERNEL_RADIX_SCAN, s, [&] {
+            k_digit_seg_sum<<<kRadix * nseg, kBlock, 0, s>>>(hist, int(workers), nseg, seglen, w.partial);
+        });
+    launch(PLMSS_KERNEL_RADIX_SCAN, s, [&] {
+        k_radix_digit_scan<<<kRadix * nseg, kBlock, 0, s>>>(hist, dtotal, int(workers), nseg, seglen, w.partial);
+    });
+}
 
 // One pass over `workers` blocks; cnt (device) or n (host) is the length.
 template <class Src, class Dst>
@@ -219,9 +235,7 @@ void radix_pass(Src src, Dst dst, const uint32_t* cnt, uint32_t n, unsigned work
         launch(kinds.hist, s, [&] {
             k_radix_hist<Src, false><<<workers, kBlock, 0, s>>>(src, cnt, n, shift, w.hist, info);
         });
-    launch(kinds.scan, s, [&] {
-        k_radix_digit_scan<<<kRadix, kBlock, 0, s>>>(w.hist, w.dtotal, int(workers));
-    });
+    digit_scan(w.hist, w.dtotal, workers, w, s);
     launch(scatter_kind >= 0 ? scatter_kind : kinds.scatter, s, [&] {
         k_radix_scatter<Src, Dst><<<workers, kBlock, 0, s>>>(src, dst, cnt, n, shift, w.hist, w.dtotal);
     });
@@ -315,12 +329,8 @@ void sort_order_items(const T* f, uint32_t n, int32_t* order, const Work& w, int
             k_radix_hist<Src, false, true><<<workers, kBlock, 0, s>>>(src, nullptr, n, last, w.hist, info, id_shift,
                                                                       ihist);
         });
-        launch(PLMSS_KERNEL_RADIX_SCAN, s, [&] {
-            k_radix_digit_scan<<<kRadix, kBlock, 0, s>>>(w.hist, w.dtotal, int(workers));
-        });
-        launch(PLMSS_KERNEL_RADIX_SCAN, s, [&] {
-            k_radix_digit_scan<<<kRadix, kBlock, 0, s>>>(ihist, itotal, int(workers));
-        });
+        digit_scan(w.hist, w.dtotal, workers, w, s);
+        digit_scan(ihist, itotal, workers, w, s);
         launch(PLMSS_KERNEL_ORDER_LAST, s, [&] {
             k_rank_partition<Src><<<workers, kBlock, 0, s>>>(src, n, last, w.hist, w.dtotal, ihist, itotal,
                                                              id_shift, parts);

@@ -28,6 +28,19 @@ __device__ __forceinline__ uint32_t load_count(const uint32_t* count_ptr, uint32
     return count_ptr ? *count_ptr : n;
 }
 
+// Worker index of this block in the radix passes.  Blocks are handed to the
+// eight XCDs in turn (block b to XCD b % 8), and neighbouring workers write
+// neighbouring parts of every digit's output range; numbering the workers
+// so that each XCD holds one contiguous run of them keeps the cache lines
+// two neighbours share in one XCD's L2, where their partial writes merge.
+// A bijection of [0, gridDim.x).
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_worker() {
+    const uint32_t b = blockIdx.x, nb = gridDim.x;
+    const uint32_t q = nb / kXcds, r = nb % kXcds, x = b % kXcds, k = b / kXcds;
+    return (x < r ? x * (q + 1u) : r * (q + 1u) + (x - r) * q) + k;
+}
+
 // Slice [lo, hi) of worker b out of nworkers, in whole tiles.
 __device__ __forceinline__ void worker_range(uint32_t count, uint32_t b, uint32_t nworkers,
                                              uint32_t tile, uint32_t* lo, uint32_t* hi) {
@@ -173,7 +186,8 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(Src src, const uint32_t* 
     if (t == 0) nan_seen = 0;
     __syncthreads();
     uint32_t lo, hi;
-    worker_range(load_count(count_ptr, n), blockIdx.x, gridDim.x, kTile, &lo, &hi);
+    const uint32_t wk = xcd_worker();
+    worker_range(load_count(count_ptr, n), wk, gridDim.x, kTile, &lo, &hi);
     bool bad = false;
     for (uint32_t tile = lo; tile < hi; tile += kTile) {
         K key[kItems];
@@ -206,39 +220,74 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(Src src, const uint32_t* 
     uint32_t s = 0;
 #pragma unroll
     for (int i = 0; i < kWavesPerBlock; ++i) s += h[i][t];
-    hist[size_t(t) * gridDim.x + blockIdx.x] = s;
+    hist[size_t(t) * gridDim.x + wk] = s;
     if (IDS) {
         uint32_t c = 0;
 #pragma unroll
         for (int i = 0; i < kWavesPerBlock; ++i) c += hi_ids[IDS ? i : 0][t];
-        ihist[size_t(t) * gridDim.x + blockIdx.x] = c;
+        ihist[size_t(t) * gridDim.x + wk] = c;
     }
     if (CHECK_NAN && t == 0 && nan_seen && info) info[0] = -4;  // PLMSS_E_NAN
 }
 
-// One block per digit: exclusive scan of hist[d][0..workers) in place; dtotal[d]
-// receives the row sum.
-__global__ __launch_bounds__(kBlock) void k_radix_digit_scan(uint32_t* hist, uint32_t* dtotal,
-                                                             int workers) {
+// Exclusive scan of each digit's row hist[d][0..workers) in place; dtotal[d]
+// receives the row sum.  A long row is split into nseg segments of seglen
+// entries, one block each (block b: digit b / nseg, segment b % nseg):
+// k_digit_seg_sum adds up every segment into segsum[b], then
+// k_radix_digit_scan scans each segment starting from the sum of the
+// segments before it.  With nseg = 1 the second kernel alone scans the row.
+constexpr int kSegment = 2048;     // preferred segment length
+constexpr int kMaxSegments = 16;   // kRadix x 16 segment sums fit u32[kMaxWorkers]
+
+__global__ __launch_bounds__(kBlock) void k_digit_seg_sum(const uint32_t* hist, int workers, int nseg, int seglen,
+                                                          uint32_t* segsum) {
     __shared__ uint32_t tmp[kWavesPerBlock];
-    uint32_t* row = hist + size_t(blockIdx.x) * workers;
-    uint32_t run = 0;
-    for (int base = 0; base < workers; base += kBlock * 4) {
+    const int d = blockIdx.x / nseg, sg = blockIdx.x % nseg;
+    const uint32_t* row = hist + size_t(d) * workers;
+    const int lo = sg * seglen, hi = min(lo + seglen, workers);
+    uint32_t sum = 0;
+    for (int base = lo; base < hi; base += kBlock * 4) {
+        uint32_t c[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) c[i] = row[min(base + i * kBlock + int(threadIdx.x), hi - 1)];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sum += base + i * kBlock + int(threadIdx.x) < hi ? c[i] : 0u;
+    }
+    uint32_t tot;
+    block_exclusive_scan(sum, tmp, &tot);
+    if (threadIdx.x == 0) segsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_radix_digit_scan(uint32_t* hist, uint32_t* dtotal, int workers,
+                                                             int nseg, int seglen, const uint32_t* segsum) {
+    __shared__ uint32_t tmp[kWavesPerBlock];
+    const int d = blockIdx.x / nseg, sg = blockIdx.x % nseg;
+    uint32_t* row = hist + size_t(d) * workers;
+    const int lo = sg * seglen, hi = min(lo + seglen, workers);
+    uint32_t run = 0, total = 0;
+    for (int k = 0; k < nseg && nseg > 1; ++k) {
+        const uint32_t v = segsum[d * nseg + k];
+        run += k < sg ? v : 0u;
+        total += v;
+    }
+    for (int base = lo; base < hi; base += kBlock * 4) {
         // four consecutive entries per thread per round, loads issued together
         const int beg = base + threadIdx.x * 4;
         uint32_t c[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) c[i] = (beg + i < workers) ? row[beg + i] : 0u;
+        for (int i = 0; i < 4; ++i) c[i] = row[min(beg + i, hi - 1)];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) c[i] = beg + i < hi ? c[i] : 0u;
         uint32_t tot;
         uint32_t e = run + block_exclusive_scan(c[0] + c[1] + c[2] + c[3], tmp, &tot);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            if (beg + i < workers) row[beg + i] = e;
+            if (beg + i < hi) row[beg + i] = e;
             e += c[i];
         }
         run += tot;
     }
-    if (threadIdx.x == 0) dtotal[blockIdx.x] = run;
+    if (threadIdx.x == 0 && sg == 0) dtotal[d] = nseg > 1 ? total : run;
 }
 
 template <typename K>
@@ -264,22 +313,28 @@ __global__ __launch_bounds__(kBlock, sizeof(typename Src::key_t) == 4 ? 4 : 2) v
     const int t = threadIdx.x, w = wave_id(), lane = lane_id();
     uint32_t tot;
     const uint32_t base = block_exclusive_scan(dtotal[t], sm.tmp, &tot);
-    sm.run[t] = base + hist[size_t(t) * gridDim.x + blockIdx.x];
+    const uint32_t wk = xcd_worker();
+    sm.run[t] = base + hist[size_t(t) * gridDim.x + wk];
     uint32_t lo, hi;
-    worker_range(load_count(count_ptr, n), blockIdx.x, gridDim.x, kTile, &lo, &hi);
+    worker_range(load_count(count_ptr, n), wk, gridDim.x, kTile, &lo, &hi);
     const uint64_t lt = lanemask_lt();
-    for (uint32_t tile = lo; tile < hi; tile += kTile) {
+    // wave w owns keys [w*64*kItems, (w+1)*64*kItems) of a tile, row i of the
+    // wave holds 64 consecutive keys: (w, i, lane) is the input order.  Loads
+    // use indices clamped into the slice, so all of a tile's loads issue
+    // before the first wait; a tile's loads are issued while the tile before
+    // it is still being written out.
+    K key[kItems];
+    uint32_t val[kItems];
+    auto load_tile = [&](uint32_t tl) {
+        const uint32_t base = tl + uint32_t(w) * kWave * kItems + lane;
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) load_item(src, min(base + uint32_t(i) * kWave, hi - 1u), key[i], val[i]);
+    };
+    auto step = [&](uint32_t tile) {
         const uint32_t tsize = min(uint32_t(kTile), hi - tile);
 #pragma unroll
         for (int i = 0; i < kWavesPerBlock; ++i) sm.wcnt[i][t] = 0;
-        // wave w owns keys [w*64*kItems, (w+1)*64*kItems) of the tile, row i of
-        // the wave holds 64 consecutive keys: (w, i, lane) is the input order
-        K key[kItems];
-        uint32_t val[kItems];
         const uint32_t wbase = tile + uint32_t(w) * kWave * kItems + lane;
-        // clamped indices: all loads issue before the first wait
-#pragma unroll
-        for (int i = 0; i < kItems; ++i) load_item(src, min(wbase + uint32_t(i) * kWave, hi - 1u), key[i], val[i]);
         __syncthreads();
         // rank inside the wave: the highest lane of each digit group adds the
         // group's size to the wave's counter and gets the count before it;
@@ -330,19 +385,30 @@ __global__ __launch_bounds__(kBlock, sizeof(typename Src::key_t) == 4 ? 4 : 2) v
                 sm.vals[p] = val[i];
             }
         }
+        // the items are in LDS: their registers take the next tile
+        if (tile + kTile < hi) load_tile(tile + kTile);
         __syncthreads();
+        // every thread stores kItems items: past the tile's end it repeats
+        // the tile's last item (same address, same value), so the number of
+        // stores after the next tile's loads is fixed and waiting for those
+        // loads does not wait for the stores
 #pragma unroll
         for (int i = 0; i < kItems; ++i) {
-            const uint32_t j = uint32_t(i) * kBlock + t;
-            if (j < tsize) {
-                const K k = sm.keys[j];
-                const uint32_t d = digit_of(k, shift);
-                dst.put(sm.run[d] + (j - sm.tstart[d]), k, sm.vals[j]);
-            }
+            const uint32_t j = min(uint32_t(i) * kBlock + t, tsize - 1u);
+            const K k = sm.keys[j];
+            const uint32_t d = digit_of(k, shift);
+            dst.put(sm.run[d] + (j - sm.tstart[d]), k, sm.vals[j]);
         }
         __syncthreads();
         sm.run[t] += sm.tcount[t];
+    };
+    // the first tile is peeled off, so that every pass through the loop
+    // starts with the same memory operations in flight
+    if (lo < hi) {
+        load_tile(lo);
+        step(lo);
     }
+    for (uint32_t tile = lo + kTile; tile < hi; tile += kTile) step(tile);
 }
 
 // Last pass of the order field without a scattered write over the whole
@@ -350,9 +416,9 @@ __global__ __launch_bounds__(kBlock, sizeof(typename Src::key_t) == 4 ? 4 : 2) v
 // the top digit as in k_radix_scatter, and the pair (id, position) is then
 // written to one of 256 id ranges (id >> id_shift), so that k_invert_ranges
 // writes order[] one range at a time.  ihist/itotal: the per-worker id-range
-// counts and their totals (k_radix_hist with IDS, then k_radix_digit_scan).
+// counts and their totals (k_radix_hist with IDS, then the digit scan).
 template <class Src>
-__global__ __launch_bounds__(kBlock) void k_rank_partition(Src src, uint32_t n, int shift,
+__global__ __launch_bounds__(kBlock, 3) void k_rank_partition(Src src, uint32_t n, int shift,
                                                            const uint32_t* hist, const uint32_t* dtotal,
                                                            const uint32_t* ihist, const uint32_t* itotal,
                                                            int id_shift, uint64_t* out) {
@@ -364,22 +430,28 @@ __global__ __launch_bounds__(kBlock) void k_rank_partition(Src src, uint32_t n, 
     __shared__ uint32_t tmp[kWavesPerBlock];
     const int t = threadIdx.x, w = wave_id(), lane = lane_id();
     uint32_t tot;
-    run[t] = block_exclusive_scan(dtotal[t], tmp, &tot) + hist[size_t(t) * gridDim.x + blockIdx.x];
-    irun[t] = block_exclusive_scan(itotal[t], tmp, &tot) + ihist[size_t(t) * gridDim.x + blockIdx.x];
+    const uint32_t wk = xcd_worker();
+    run[t] = block_exclusive_scan(dtotal[t], tmp, &tot) + hist[size_t(t) * gridDim.x + wk];
+    irun[t] = block_exclusive_scan(itotal[t], tmp, &tot) + ihist[size_t(t) * gridDim.x + wk];
     uint32_t lo, hi;
-    worker_range(n, blockIdx.x, gridDim.x, kTile, &lo, &hi);
+    worker_range(n, wk, gridDim.x, kTile, &lo, &hi);
     const uint64_t lt = lanemask_lt();
-    for (uint32_t tile = lo; tile < hi; tile += kTile) {
+    // tiles are loaded as in k_radix_scatter: clamped indices, and the next
+    // tile's loads issued before the current tile is written out
+    K key[kItems];
+    uint32_t val[kItems];
+    auto load_tile = [&](uint32_t tl) {
+        const uint32_t base = tl + uint32_t(w) * kWave * kItems + lane;
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) load_item(src, min(base + uint32_t(i) * kWave, hi - 1u), key[i], val[i]);
+    };
+    auto step = [&](uint32_t tile) {
         const uint32_t tsize = min(uint32_t(kTile), hi - tile);
 #pragma unroll
         for (int i = 0; i < kWavesPerBlock; ++i) wcnt[i][t] = 0;
         icount[t] = 0;
         ifill[t] = 0;
-        K key[kItems];
-        uint32_t val[kItems];
         const uint32_t wbase = tile + uint32_t(w) * kWave * kItems + lane;
-#pragma unroll
-        for (int i = 0; i < kItems; ++i) load_item(src, min(wbase + uint32_t(i) * kWave, hi - 1u), key[i], val[i]);
         __syncthreads();
         uint32_t local[kItems], prior[kItems];
 #pragma unroll
@@ -428,20 +500,26 @@ __global__ __launch_bounds__(kBlock) void k_rank_partition(Src src, uint32_t n, 
                 stage[slot] = (uint64_t(val[i]) << 32) | pos;
             }
         }
+        if (tile + kTile < hi) load_tile(tile + kTile);
         __syncthreads();
+        // stores as in k_radix_scatter: kItems per thread, the last item
+        // repeated past the tile's end
 #pragma unroll
         for (int i = 0; i < kItems; ++i) {
-            const uint32_t j = uint32_t(i) * kBlock + t;
-            if (j < tsize) {
-                const uint64_t x = stage[j];
-                const uint32_t r = uint32_t(x >> 32) >> id_shift;
-                out[irun[r] + (j - istart[r])] = x;
-            }
+            const uint32_t j = min(uint32_t(i) * kBlock + t, tsize - 1u);
+            const uint64_t x = stage[j];
+            const uint32_t r = uint32_t(x >> 32) >> id_shift;
+            out[irun[r] + (j - istart[r])] = x;
         }
         __syncthreads();
         run[t] += tcount[t];
         irun[t] += icount[t];
+    };
+    if (lo < hi) {
+        load_tile(lo);
+        step(lo);
     }
+    for (uint32_t tile = lo + kTile; tile < hi; tile += kTile) step(tile);
 }
 
 // The inversion order[id] = position by id chunks of kChunk ids, each

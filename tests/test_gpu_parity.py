@@ -181,9 +181,13 @@ def test_compress_long_chain(torch):
     assert (_host(d) == n - 1).all() and (_host(a) == np.arange(n)).all()
 
 
-def test_config_3d_256_full_oracle(torch):
+@pytest.mark.parametrize("with_order", [False, True])
+def test_config_3d_256_full_oracle(torch, with_order):
+    """256^3 against the oracle element by element; with the order field this
+    also covers the digit scans split over several blocks per digit (4096
+    radix workers)."""
     f = fields.workload_c2(256)
-    _compare_full(torch, f, False, "c2-256")
+    _compare_full(torch, f, with_order, f"c2-256 order={with_order}")
 
 
 def test_config_3d_512_sampled(torch):
