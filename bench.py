@@ -156,6 +156,25 @@ def timed_region(step, steps, torch, lib=None, trace=None, max_launches=0):
     return (t1 - t0) * 1e3, launches
 
 
+def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
+    """Achieved device-to-device copy rate in GB/s (bytes read + written)."""
+    src = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    times = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        times.append(a.elapsed_time(b))
+    times.sort()
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (times[len(times) // 2] * 1e-3) / 1e9
+
+
 def per_kernel(launches, steps):
     agg = {}
     for name, ms in launches:
@@ -348,11 +367,18 @@ def main():
     if info[0] != 0:
         raise RuntimeError(f"device status {info[0]}")
 
+    # the throughput comes from untraced steps; the per-kernel times from the
+    # same number of steps again with a HIP event pair around every launch
+    # (the events add a little time of their own)
     log(f"timing {args.steps} full steps")
-    wall_full, launches = timed_region(step_full, args.steps, torch, lib, trace, max_launches)
+    wall_full, _ = timed_region(step_full, args.steps, torch)
     log(f"timing {args.steps} label-only steps")
-    wall_labels, launches_l = timed_region(step_labels, args.steps, torch, lib, trace, max_launches)
+    wall_labels, _ = timed_region(step_labels, args.steps, torch)
+    log(f"timing {args.steps} full and {args.steps} label-only steps with per-kernel events")
+    wall_full_traced, launches = timed_region(step_full, args.steps, torch, lib, trace, max_launches)
+    wall_labels_traced, launches_l = timed_region(step_labels, args.steps, torch, lib, trace, max_launches)
     lib.plmss_trace_destroy(trace)
+    copy_gbs = copy_bandwidth(torch)
 
     ms_step = wall_full / args.steps
     value = n / (ms_step * 1e-3) / 1e6
@@ -376,7 +402,9 @@ def main():
                 "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
                 "traffic_source": traffic_src, "avg_launch_ms": avg_ms,
                 "algorithmic_bytes_per_launch": per_launch_bytes, "basis": basis,
-                "kernel_source_digest": kernel_source_digest()}
+                "kernel_source_digest": kernel_source_digest(),
+                "copy_probe_gbs": copy_gbs,
+                "copy_probe": "device-to-device copy of 1 GiB (read + write bytes / time), median of 5"}
 
     # CPU baseline: the oracle on a bounded slab of the same field, one core
     cpu = None
@@ -412,6 +440,8 @@ def main():
         "labels_only": {"value": labels_value, "ms_per_step": ms_step_l,
                         "path_frac_of_hbm_roofline": n * 48.0 / (ms_step_l * 1e-3) / (HBM_PEAK_GBS * 1e9),
                         "note": "same labels, order field not materialised (vertex order compared in place)"},
+        "ms_per_step_traced": wall_full_traced / args.steps,
+        "ms_per_step_labels_only_traced": wall_labels_traced / args.steps,
         "kernels_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in sorted(kern.items())},
         "kernels_ms_per_step_labels_only": {k: round(v["ms_per_step"], 4) for k, v in sorted(kern_l.items())},
         "batched": batched,
