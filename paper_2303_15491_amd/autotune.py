@@ -39,7 +39,7 @@ SPACE = {
 }
 
 SEGMENT_KNOBS = ("scan_depth", "scan_rounds", "sort_workers")
-ORDER_KNOBS = ("order_invert", "order_packed", "order_workers")
+ORDER_KNOBS = ("order_workers", "order_invert", "order_packed")
 BATCH_KNOBS = ("persist_blocks", "scan_depth", "scan_rounds", "sort_workers")
 
 # a candidate replaces the current setting only when it is this much faster,

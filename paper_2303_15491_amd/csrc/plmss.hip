@@ -450,11 +450,11 @@ void launch_chase_cls(int c, const Fields& F, unsigned grid, uint32_t* U, uint32
     uint64_t* rec = reinterpret_cast<uint64_t*>(w.keys[1]);
     launch(PLMSS_KERNEL_JUMP, s, [&] {
         if (c == 0)
-            k_chase<JTile3, CHASE><<<grid, kBlock, 0, s>>>(F, U, D, bn, rec, w.vals[0], w.counters + 0);
+            k_chase<JTile3, CHASE><<<grid, kChaseBlock, 0, s>>>(F, U, D, bn, rec, w.vals[0], w.counters + 0);
         else if (c == 1)
-            k_chase<JTile2, CHASE><<<grid, kBlock, 0, s>>>(F, U, D, bn, rec, w.vals[0], w.counters + 0);
+            k_chase<JTile2, CHASE><<<grid, kChaseBlock, 0, s>>>(F, U, D, bn, rec, w.vals[0], w.counters + 0);
         else
-            k_chase<JTile1, CHASE><<<grid, kBlock, 0, s>>>(F, U, D, bn, rec, w.vals[0], w.counters + 0);
+            k_chase<JTile1, CHASE><<<grid, kChaseBlock, 0, s>>>(F, U, D, bn, rec, w.vals[0], w.counters + 0);
     });
 }
 

@@ -295,6 +295,7 @@ __global__ __launch_bounds__(kBlock) void k_steepest(Fields F, uint32_t* up, uin
     __shared__ uint32_t lp[TV];  // local pointers: up in the low half, dn in the high half
     __shared__ int32_t off_tab[16];  // vertex-id offset of each neighbour code
     __shared__ uint32_t loc_tab[16];  // in-tile move of each neighbour code
+    __shared__ uint32_t row_off[RESOLVE ? ZC * TY : 1];  // vertex-id offset of each tile row from the tile's first
     __shared__ uint32_t cnt_min, cnt_max;
     __shared__ int nan_seen;
     const int t = threadIdx.x, w = wave_id(), lane = lane_id();
@@ -487,6 +488,11 @@ __global__ __launch_bounds__(kBlock) void k_steepest(Fields F, uint32_t* up, uin
         pn = tmp;
     }
     if (RESOLVE) {
+        // the write-out turns local indices into vertex ids through this
+        // table (row = plane * TY + row in plane) instead of two 32-bit
+        // multiplies per pointer
+        for (int i = t; i < ZC * TY; i += kBlock)
+            row_off[RESOLVE ? i : 0] = uint32_t(i / TY) * uint32_t(S) + uint32_t(i % TY) * uint32_t(g.nx);
         __syncthreads();
         // entries of this thread: (lz, row) pairs over the tile's planes; entry
         // e has local index li0 + (e / RPW) * TY * kTX + (e % RPW) * kTX
@@ -560,8 +566,7 @@ __global__ __launch_bounds__(kBlock) void k_steepest(Fields F, uint32_t* up, uin
         const uint32_t tile0 =
             vbase + uint32_t(z0) * uint32_t(S) + uint32_t(y0) * uint32_t(g.nx) + uint32_t(x0);
         auto gid = [&](uint32_t li) -> uint32_t {
-            const uint32_t ax = li & (kTX - 1), ay = (li / kTX) & (TY - 1), az = li / (kTX * TY);
-            return tile0 + az * uint32_t(S) + ay * uint32_t(g.nx) + ax;
+            return tile0 + row_off[RESOLVE ? li / kTX : 0] + (li & (kTX - 1));
         };
         // p: the vertex's pointer; q: the pointer of p's vertex; v: the vertex
         auto resolve = [&](uint32_t v, uint32_t p, uint32_t q) -> uint32_t {
@@ -578,7 +583,7 @@ __global__ __launch_bounds__(kBlock) void k_steepest(Fields F, uint32_t* up, uin
                 const int ly = w * RPW + r, y = y0 + ly;
                 if (x >= g.nx || y >= g.ny) continue;
                 const uint32_t li = uint32_t((lz * TY + ly) * kTX + lane);
-                const uint32_t v = tile0 + uint32_t(lz) * uint32_t(S) + uint32_t(ly) * uint32_t(g.nx) + uint32_t(lane);
+                const uint32_t v = tile0 + row_off[RESOLVE ? lz * TY + ly : 0] + uint32_t(lane);
                 const uint32_t own = lp[li];
                 const uint32_t pu = own & 0xffffu, pd = own >> 16;
                 const uint32_t qu = lp[pu & (kExit - 1)] & 0xffffu, qd = lp[pd & (kExit - 1)] >> 16;
@@ -605,7 +610,7 @@ inline uint32_t steepest_tiles(int64_t nx, int64_t ny, int64_t nz, int ty, int z
 
 // ---- chase, labels and MS pair listing ----------------------------------------------
 //
-// One block per JX x JY x JZ tile (kJV = 2048 vertices, 8 per thread).  For
+// One block per JX x JY x JZ tile (kJV = 2048 vertices, 4 per thread of 512).  For
 // every vertex it finishes the tile-compressed pointers: an unresolved pointer
 // is followed from tile to tile (each hop lands on the next tile's compressed
 // pointer, and is written back so that later readers jump further) until a
@@ -617,7 +622,13 @@ inline uint32_t steepest_tiles(int64_t nx, int64_t ny, int64_t nz, int ty, int z
 // by the MS id later).  MS regions are a few vertices across, so a 3-D tile
 // lists far fewer pairs than a row of the same size would.
 constexpr int kJV = 2048;            // vertices per tile
-constexpr int kJPer = kJV / kBlock;  // per thread
+constexpr int kJPer = kJV / kBlock;  // per thread (256-thread blocks)
+// The chase runs 512-thread blocks, four vertices per thread: its pointer
+// hops are dependent gathers, and the smaller per-thread state lets twice as
+// many waves hide their latency.
+constexpr int kChaseBlock = 512;
+constexpr int kChaseWaves = kChaseBlock / kWave;
+constexpr int kChasePer = kJV / kChaseBlock;
 constexpr int kHash = kJV;           // hash slots: a tile has at most kJV distinct pairs
 constexpr uint64_t kEmpty = ~0ull;   // pair keys are < 2^62
 
@@ -656,11 +667,11 @@ __device__ __forceinline__ void jtile_xyz(const FieldDesc& fd, uint32_t lt, int 
 // CHASE: labels from the tile-compressed pointers U/D (written back as they
 // are followed).  Otherwise the labels are read from the field's desc/asc.
 template <class T, bool CHASE>
-__global__ __launch_bounds__(kBlock) void k_chase(Fields F, uint32_t* U, uint32_t* D, int bn,
+__global__ __launch_bounds__(kChaseBlock) void k_chase(Fields F, uint32_t* U, uint32_t* D, int bn,
                                                   uint64_t* rec_keys, uint32_t* rec_vals, uint32_t* rec_count) {
     __shared__ uint64_t table[kHash];
     __shared__ uint16_t dense[kHash];
-    __shared__ uint32_t tmp[kWavesPerBlock];
+    __shared__ uint32_t tmp[kChaseWaves];
     __shared__ uint32_t s_base;
     const int t = threadIdx.x, lane = lane_id(), w = wave_id();
     uint32_t tfirst, tlast;
@@ -671,13 +682,13 @@ __global__ __launch_bounds__(kBlock) void k_chase(Fields F, uint32_t* U, uint32_
         const uint32_t lt = tile - fd.jbase;
         __syncthreads();  // the previous tile's readers of LDS are done
 #pragma unroll
-        for (int i = 0; i < kHash / kBlock; ++i) table[t + i * kBlock] = kEmpty;
-        uint32_t lv[kJPer], pu[kJPer], pd[kJPer];
-        bool ok[kJPer];
+        for (int i = 0; i < kHash / kChaseBlock; ++i) table[t + i * kChaseBlock] = kEmpty;
+        uint32_t lv[kChasePer], pu[kChasePer], pd[kChasePer];
+        bool ok[kChasePer];
 #pragma unroll
-        for (int i = 0; i < kJPer; ++i) {
+        for (int i = 0; i < kChasePer; ++i) {
             int x, y, z;
-            jtile_xyz<T>(fd, lt, t + i * kBlock, &x, &y, &z);
+            jtile_xyz<T>(fd, lt, t + i * kChaseBlock, &x, &y, &z);
             ok[i] = x < fd.nx && y < fd.ny && z < fd.nz;
             lv[i] = ok[i] ? (uint32_t(z) * uint32_t(fd.ny) + uint32_t(y)) * uint32_t(fd.nx) + uint32_t(x) : 0u;
             // lanes past the field's edge read its vertex 0 (lv = 0) and drop
@@ -691,7 +702,7 @@ __global__ __launch_bounds__(kBlock) void k_chase(Fields F, uint32_t* U, uint32_
             }
         }
 #pragma unroll
-        for (int i = 0; i < kJPer; ++i) {
+        for (int i = 0; i < kChasePer; ++i) {
             pu[i] = ok[i] ? pu[i] : (CHASE ? kMark : 0u);
             pd[i] = ok[i] ? pd[i] : (CHASE ? kMark : 0u);
         }
@@ -704,9 +715,9 @@ __global__ __launch_bounds__(kBlock) void k_chase(Fields F, uint32_t* U, uint32_
             while (pending && hops < kMaxHops) {
                 // all gathers of the hop first, then the write-backs, so that
                 // no store waits on its own load before the next is issued
-                uint32_t nu[kJPer], nd[kJPer];
+                uint32_t nu[kChasePer], nd[kChasePer];
 #pragma unroll
-                for (int i = 0; i < kJPer; ++i) {
+                for (int i = 0; i < kChasePer; ++i) {
                     nu[i] = pu[i];
                     nd[i] = pd[i];
                     if (!(pu[i] & kMark)) nu[i] = gmem(U)[pu[i]];
@@ -714,7 +725,7 @@ __global__ __launch_bounds__(kBlock) void k_chase(Fields F, uint32_t* U, uint32_
                 }
                 pending = false;
 #pragma unroll
-                for (int i = 0; i < kJPer; ++i) {
+                for (int i = 0; i < kChasePer; ++i) {
                     if (!(pu[i] & kMark)) {
                         if (hops) gmem(U)[fd.vbase + lv[i]] = nu[i];
                         pending = true;
@@ -729,7 +740,7 @@ __global__ __launch_bounds__(kBlock) void k_chase(Fields F, uint32_t* U, uint32_
                 ++hops;
             }
 #pragma unroll
-            for (int i = 0; i < kJPer; ++i) {
+            for (int i = 0; i < kChasePer; ++i) {
                 pu[i] &= ~kMark;
                 pd[i] &= ~kMark;
                 if (ok[i]) {
@@ -741,9 +752,9 @@ __global__ __launch_bounds__(kBlock) void k_chase(Fields F, uint32_t* U, uint32_
         }
         __syncthreads();
         // insert every vertex's pair; slot[i] = its hash slot
-        uint32_t slot[kJPer];
+        uint32_t slot[kChasePer];
 #pragma unroll
-        for (int i = 0; i < kJPer; ++i) {
+        for (int i = 0; i < kChasePer; ++i) {
             slot[i] = 0;
             if (!ok[i]) continue;
             const uint64_t key = (uint64_t(pd[i]) << bn) | uint64_t(pu[i]);
@@ -762,19 +773,19 @@ __global__ __launch_bounds__(kBlock) void k_chase(Fields F, uint32_t* U, uint32_
             slot[i] = h;
         }
         __syncthreads();
-        // number the occupied slots: wave w scans slots [w*kHash/4, (w+1)*kHash/4)
+        // number the occupied slots: wave w scans slots [w*kHash/8, (w+1)*kHash/8)
         // row by row (64 consecutive slots per row), so LDS reads are conflict-free
-        constexpr int kRows = kHash / kBlock;
+        constexpr int kRows = kHash / kChaseBlock;
         const uint64_t lt_mask = lanemask_lt();
         uint32_t wcount = 0;
 #pragma unroll
         for (int i = 0; i < kRows; ++i)
-            wcount += uint32_t(__popcll(__ballot(table[w * (kHash / kWavesPerBlock) + i * kWave + lane] != kEmpty)));
+            wcount += uint32_t(__popcll(__ballot(table[w * (kHash / kChaseWaves) + i * kWave + lane] != kEmpty)));
         if (lane == 0) tmp[w] = wcount;
         __syncthreads();
         uint32_t j = 0, total = 0;
 #pragma unroll
-        for (int i = 0; i < kWavesPerBlock; ++i) {
+        for (int i = 0; i < kChaseWaves; ++i) {
             j += (i < w) ? tmp[i] : 0u;
             total += tmp[i];
         }
@@ -783,7 +794,7 @@ __global__ __launch_bounds__(kBlock) void k_chase(Fields F, uint32_t* U, uint32_
         const uint32_t base = s_base;
 #pragma unroll
         for (int i = 0; i < kRows; ++i) {
-            const int sl = w * (kHash / kWavesPerBlock) + i * kWave + lane;
+            const int sl = w * (kHash / kChaseWaves) + i * kWave + lane;
             const uint64_t k = table[sl];
             const uint64_t occ = __ballot(k != kEmpty);
             if (k != kEmpty) {
@@ -796,7 +807,7 @@ __global__ __launch_bounds__(kBlock) void k_chase(Fields F, uint32_t* U, uint32_
         }
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < kJPer; ++i)
+        for (int i = 0; i < kChasePer; ++i)
             if (ok[i]) gmem(fd.ms)[lv[i]] = int32_t(base + dense[slot[i]]);
     }
 }

@@ -28,18 +28,11 @@ __device__ __forceinline__ uint32_t load_count(const uint32_t* count_ptr, uint32
     return count_ptr ? *count_ptr : n;
 }
 
-// Worker index of this block in the radix passes.  Blocks are handed to the
-// eight XCDs in turn (block b to XCD b % 8), and neighbouring workers write
-// neighbouring parts of every digit's output range; numbering the workers
-// so that each XCD holds one contiguous run of them keeps the cache lines
-// two neighbours share in one XCD's L2, where their partial writes merge.
-// A bijection of [0, gridDim.x).
-constexpr uint32_t kXcds = 8;
-__device__ __forceinline__ uint32_t xcd_worker() {
-    const uint32_t b = blockIdx.x, nb = gridDim.x;
-    const uint32_t q = nb / kXcds, r = nb % kXcds, x = b % kXcds, k = b / kXcds;
-    return (x < r ? x * (q + 1u) : r * (q + 1u) + (x - r) * q) + k;
-}
+// Radix workers are numbered with xcd_block: neighbouring workers write
+// neighbouring parts of every digit's output range, and with each XCD
+// holding one contiguous run of workers the cache lines two neighbours share
+// stay in one XCD's L2, where their partial writes merge.
+__device__ __forceinline__ uint32_t xcd_worker() { return xcd_block(blockIdx.x, gridDim.x); }
 
 // Slice [lo, hi) of worker b out of nworkers, in whole tiles.
 __device__ __forceinline__ void worker_range(uint32_t count, uint32_t b, uint32_t nworkers,
@@ -547,7 +540,9 @@ __global__ __launch_bounds__(kBlock) void k_chunk_partition(const uint64_t* part
     __shared__ uint32_t tmp[kWavesPerBlock];
     __shared__ uint32_t s_first;
     const int t = threadIdx.x;
-    const uint32_t lo = blockIdx.x * uint32_t(kTile);
+    // tiles numbered XCD by XCD, so that tiles reserving neighbouring runs
+    // of a chunk mostly share an L2
+    const uint32_t lo = xcd_worker() * uint32_t(kTile);
     const uint32_t hi = min(n, lo + uint32_t(kTile));
     for (int i = t; i < kMaxRel; i += kBlock) {
         cnt[i] = 0;
