@@ -244,8 +244,9 @@ void radix_pass(Src src, Dst dst, const uint32_t* cnt, uint32_t n, unsigned work
 // Ping-pong storage of the order sort's (key, id) items: 32-bit keys packed
 // with their ids in one word, or keys and ids in two arrays.  The packed form
 // halves the write streams of a scatter, the split form halves what a
-// histogram reads; so the packed storage turns split for the last pass (the
-// pass before it writes keys and ids into the two halves of one buffer).
+// histogram of keys alone reads; so the packed storage turns split for a last
+// pass whose histogram reads only keys (the pass before it writes keys and
+// ids into the two halves of one buffer).
 struct PackedItems {
     uint64_t* kv[2];
     uint32_t* ids_buf;
@@ -285,6 +286,42 @@ struct SplitItems {
 // grouped by id range, k_chunk_partition regroups them by chunk of kChunk
 // ids, k_invert_chunks inverts each chunk in LDS); or as sorted ids inverted
 // by `windows` launches over parts of the id range.
+// Last pass of the order field and the inversion by id chunks: the last
+// pass writes (id, position) pairs grouped by id range to parts,
+// k_chunk_partition regroups them by chunk into parts2, k_invert_chunks
+// writes each chunk of order[] from LDS.
+template <class Src>
+void invert_by_chunks(Src src, uint32_t n, unsigned workers, int last, uint64_t* parts, uint64_t* parts2,
+                      int32_t* order, const Work& w, int32_t* info, hipStream_t s) {
+    // id ranges of 1 to 256 chunks, at most 64 of them below 2^29 vertices
+    // (longer write runs) and 256 above; ihist (256 x workers <= npad
+    // entries) in rank_of, which the order sort does not otherwise use
+    const int id_shift = std::min(kChunkBits + 8, std::max(kChunkBits, bit_width(uint64_t(n) - 1) - 6));
+    const unsigned tiles = unsigned(n_tiles(n));
+    uint32_t* ihist = w.rank_of;
+    uint32_t* itotal = w.sortaux;
+    uint32_t* chunk_fill = w.sortaux + kRadix;
+    const uint32_t chunks = uint32_t((uint64_t(n) + kChunk - 1) / kChunk);
+    launch(PLMSS_KERNEL_ORDER_HIST, s, [&] {
+        k_radix_hist<Src, false, true><<<workers, kBlock, 0, s>>>(src, nullptr, n, last, w.hist, info, id_shift,
+                                                                  ihist);
+    });
+    digit_scan(w.hist, w.dtotal, workers, w, s);
+    digit_scan(ihist, itotal, workers, w, s);
+    launch(PLMSS_KERNEL_ORDER_LAST, s, [&] {
+        k_rank_partition<Src><<<workers, kBlock, 0, s>>>(src, n, last, w.hist, w.dtotal, ihist, itotal, id_shift,
+                                                         parts);
+    });
+    launch(PLMSS_KERNEL_MISC, s, [&] {
+        k_zero_u32<<<std::min(256u, (chunks + kBlock - 1) / kBlock), kBlock, 0, s>>>(chunk_fill, chunks);
+    });
+    launch(PLMSS_KERNEL_ORDER_REGROUP, s, [&] {
+        k_chunk_partition<<<tiles, kBlock, 0, s>>>(parts, n, id_shift, chunk_fill, parts2);
+    });
+    launch(PLMSS_KERNEL_ORDER_INVERT, s,
+           [&] { k_invert_chunks<<<chunks, kInvertBlock, 0, s>>>(parts2, n, order); });
+}
+
 template <typename T, typename K, class Items>
 void sort_order_items(const T* f, uint32_t n, int32_t* order, const Work& w, int32_t* info, hipStream_t s,
                       const Items& it) {
@@ -297,7 +334,10 @@ void sort_order_items(const T* f, uint32_t n, int32_t* order, const Work& w, int
                PLMSS_KERNEL_ORDER_FIRST);
     int cur = 0;
     for (int p = 1; p < passes - 1; ++p) {
-        if (p == passes - 2)
+        // the by-chunk inversion's histogram reads the ids with the keys, so
+        // the items stay packed to the end; the other inversions' histograms
+        // read only keys, which the pass before the last splits off
+        if (p == passes - 2 && inv != 1)
             radix_pass(it.src(cur), it.split_dst(cur ^ 1), nullptr, n, workers, kRadixBits * p, false, w, info, s,
                        kOrderKinds);
         else
@@ -306,43 +346,16 @@ void sort_order_items(const T* f, uint32_t n, int32_t* order, const Work& w, int
         cur ^= 1;
     }
     const int last = kRadixBits * (passes - 1);
+    if (inv == 1) {
+        // the pairs go to it.spare(cur); it.own(cur) is free once the last
+        // pass has read it
+        invert_by_chunks(it.src(cur), n, workers, last, it.spare(cur), it.own(cur), order, w, info, s);
+        return;
+    }
     const auto src = it.last_src(cur);
-    using Src = decltype(it.last_src(0));
     if (inv == 0) {
         radix_pass(src, RankDst<K>{order}, nullptr, n, workers, last, false, w, info, s, kOrderKinds,
                    PLMSS_KERNEL_ORDER_INVERT);
-        return;
-    }
-    if (inv == 1) {
-        // id ranges of 1 to 256 chunks, at most 64 of them below 2^29
-        // vertices (longer write runs) and 256 above; ihist (256 x workers <=
-        // npad entries) in rank_of, which the order sort does not otherwise use
-        const int id_shift =
-            std::min(kChunkBits + 8, std::max(kChunkBits, bit_width(uint64_t(n) - 1) - 6));
-        uint32_t* ihist = w.rank_of;
-        uint32_t* itotal = w.sortaux;
-        uint32_t* chunk_fill = w.sortaux + kRadix;
-        const uint32_t chunks = uint32_t((uint64_t(n) + kChunk - 1) / kChunk);
-        uint64_t* parts = it.spare(cur);
-        uint64_t* parts2 = it.own(cur);  // free once the last pass has read it
-        launch(PLMSS_KERNEL_ORDER_HIST, s, [&] {
-            k_radix_hist<Src, false, true><<<workers, kBlock, 0, s>>>(src, nullptr, n, last, w.hist, info, id_shift,
-                                                                      ihist);
-        });
-        digit_scan(w.hist, w.dtotal, workers, w, s);
-        digit_scan(ihist, itotal, workers, w, s);
-        launch(PLMSS_KERNEL_ORDER_LAST, s, [&] {
-            k_rank_partition<Src><<<workers, kBlock, 0, s>>>(src, n, last, w.hist, w.dtotal, ihist, itotal,
-                                                             id_shift, parts);
-        });
-        launch(PLMSS_KERNEL_MISC, s, [&] {
-            k_zero_u32<<<std::min(256u, (chunks + kBlock - 1) / kBlock), kBlock, 0, s>>>(chunk_fill, chunks);
-        });
-        launch(PLMSS_KERNEL_ORDER_REGROUP, s, [&] {
-            k_chunk_partition<<<tiles, kBlock, 0, s>>>(parts, n, id_shift, chunk_fill, parts2);
-        });
-        launch(PLMSS_KERNEL_ORDER_INVERT, s,
-               [&] { k_invert_chunks<<<chunks, kInvertBlock, 0, s>>>(parts2, n, order); });
         return;
     }
     uint32_t* ids = it.ids(cur);
