@@ -448,7 +448,11 @@ void launch_steepest_cls(int c, int zc, const Fields& F, unsigned grid, uint32_t
 template <bool RESOLVE>
 void launch_steepest_any(int c, int zc, const Fields& F, unsigned grid, int32_t dtype, bool order,
                          uint32_t* up, uint32_t* dn, hipStream_t s) {
-    if (order)
+    // ranks of a field below 2^28 vertices leave four bits for the code
+    const bool packed = order && uint64_t(F.one.nx) * uint64_t(F.one.ny) * uint64_t(F.one.nz) < (1ull << 28);
+    if (packed)
+        launch_steepest_cls<RESOLVE, RankOrderPacked>(c, zc, F, grid, up, dn, s);
+    else if (order)
         launch_steepest_cls<RESOLVE, RankOrder>(c, zc, F, grid, up, dn, s);
     else if (dtype == PLMSS_F32)
         launch_steepest_cls<RESOLVE, FieldOrder<float, uint32_t>>(c, zc, F, grid, up, dn, s);

@@ -20,6 +20,7 @@ struct FieldOrder {
     using key_t = K;
     using raw_t = T;
     static constexpr bool kCheckNan = true;
+    static constexpr bool kPackedCodes = false;
     const T* f;
     static __device__ __forceinline__ FieldOrder from(const void* p) { return {static_cast<const T*>(p)}; }
     __device__ __forceinline__ T fetch(size_t i) const { return gmem(f)[i]; }
@@ -35,10 +36,23 @@ struct RankOrder {
     using key_t = uint32_t;
     using raw_t = int32_t;
     static constexpr bool kCheckNan = false;
+    static constexpr bool kPackedCodes = false;
     const int32_t* order;
     static __device__ __forceinline__ RankOrder from(const void* p) { return {static_cast<const int32_t*>(p)}; }
     __device__ __forceinline__ int32_t fetch(size_t i) const { return gmem(order)[i]; }
     static __device__ __forceinline__ uint32_t key(int32_t a, bool&) { return uint32_t(a) + 1u; }
+};
+
+// The same order field when every rank is below 2^28 - 1 (fields of fewer
+// than 2^28 vertices): a key and a neighbour code then share one 32-bit word,
+// (key << 4) | code, and the steepest candidate is a plain unsigned max (min)
+// of such words.  No tie rule is needed: ranks are distinct, and the only
+// candidate seen twice, the vertex itself, carries the same code both times.
+struct RankOrderPacked : RankOrder {
+    static constexpr bool kPackedCodes = true;
+    static __device__ __forceinline__ RankOrderPacked from(const void* p) {
+        return {{static_cast<const int32_t*>(p)}};
+    }
 };
 
 struct GridDims {
@@ -280,6 +294,7 @@ template <class Src, int TY, int ZC, bool RESOLVE>
 __global__ __launch_bounds__(kBlock) void k_steepest(Fields F, uint32_t* up, uint32_t* dn, int rounds) {
     using K = typename Src::key_t;
     constexpr bool kSquares = sizeof(K) == 4;
+    constexpr bool kPacked = kSquares && Src::kPackedCodes;
     constexpr int PX = kTX + 2, PY = TY + 2, RPW = TY / kWavesPerBlock;
     constexpr int TV = RESOLVE ? kTX * TY * ZC : 1;
     constexpr int kLoads = (PY * PX + kBlock - 1) / kBlock;
@@ -376,20 +391,30 @@ __global__ __launch_bounds__(kBlock) void k_steepest(Fields F, uint32_t* up, uin
                 uint32_t th = 0, tl = 0;
                 if (exists) {
                     const K a[4] = {pl[0][r][c], pl[0][r][c + 1], pl[0][r + 1][c], pl[0][r + 1][c + 1]};
+                    if constexpr (kPacked) {
+                        // (key << 4) | position; the minimum of (key - 1): a
+                        // position outside the grid (key 0) becomes the largest
+                        hi = max(max((a[0] << 4) | 0u, (a[1] << 4) | 1u), max((a[2] << 4) | 2u, (a[3] << 4) | 3u));
+                        lo = min(min(((a[0] - 1u) << 4) | 0u, ((a[1] - 1u) << 4) | 1u),
+                                 min(((a[2] - 1u) << 4) | 2u, ((a[3] - 1u) << 4) | 3u));
+                    } else {
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const bool gh = a[q] >= hi;
-                        hi = gh ? a[q] : hi;
-                        th = gh ? uint32_t(q) : th;
-                        const K am = a[q] - K(1);
-                        const bool gl = am < lo;
-                        lo = gl ? am : lo;
-                        tl = gl ? uint32_t(q) : tl;
+                        for (int q = 0; q < 4; ++q) {
+                            const bool gh = a[q] >= hi;
+                            hi = gh ? a[q] : hi;
+                            th = gh ? uint32_t(q) : th;
+                            const K am = a[q] - K(1);
+                            const bool gl = am < lo;
+                            lo = gl ? am : lo;
+                            tl = gl ? uint32_t(q) : tl;
+                        }
                     }
+                } else if constexpr (kPacked) {
+                    lo = ~K(15);  // low bits clear: adding a code base cannot wrap
                 }
                 sq.mx[slot][r][c] = hi;
                 sq.mn[slot][r][c] = lo;
-                sq.tag[slot][r][c] = uint8_t(th | (tl << 2));
+                if constexpr (!kPacked) sq.tag[slot][r][c] = uint8_t(th | (tl << 2));
             }
         }
     };
@@ -439,16 +464,28 @@ __global__ __launch_bounds__(kBlock) void k_steepest(Fields F, uint32_t* up, uin
                 K bu = K(0), bd = ~K(0);
                 cu = kSelf;
                 cd = kSelf;
+                if constexpr (kPacked) {
+                    // the code is the square's base plus the winner's
+                    // position, kept in the low four bits (at most 14)
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const K h = sq.mx[sl[k]][rr[k]][cc[k]];
-                    const K l = sq.mn[sl[k]][rr[k]][cc[k]];
-                    const uint32_t tg = sq.tag[sl[k]][rr[k]][cc[k]];
-                    const bool gu = h >= bu, gd = l < bd;
-                    bu = gu ? h : bu;
-                    cu = gu ? base[k] + int(tg & 3u) : cu;
-                    bd = gd ? l : bd;
-                    cd = gd ? base[k] + int(tg >> 2) : cd;
+                    for (int k = 0; k < 4; ++k) {
+                        bu = max(bu, sq.mx[sl[k]][rr[k]][cc[k]] + K(base[k]));
+                        bd = min(bd, sq.mn[sl[k]][rr[k]][cc[k]] + K(base[k]));
+                    }
+                    cu = int(bu & 15u);
+                    cd = int(bd & 15u);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const K h = sq.mx[sl[k]][rr[k]][cc[k]];
+                        const K l = sq.mn[sl[k]][rr[k]][cc[k]];
+                        const uint32_t tg = sq.tag[sl[k]][rr[k]][cc[k]];
+                        const bool gu = h >= bu, gd = l < bd;
+                        bu = gu ? h : bu;
+                        cu = gu ? base[k] + int(tg & 3u) : cu;
+                        bd = gd ? l : bd;
+                        cd = gd ? base[k] + int(tg >> 2) : cd;
+                    }
                 }
             } else {
                 const bool ym = y > 0, yp = y < g.ny - 1;
