@@ -183,6 +183,38 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(Src src, const uint32_t* 
     worker_range(load_count(count_ptr, n), wk, gridDim.x, kTile, &lo, &hi);
     bool bad = false;
     for (uint32_t tile = lo; tile < hi; tile += kTile) {
+        if constexpr (std::is_same<Src, PackedSrc>::value) {
+            // counting order is free: each lane reads two consecutive packed
+            // items per 16-byte load (key in the high word).  A pair starting
+            // at or past the slice end reads the slice's last even pair
+            // instead and counts nothing.
+            constexpr int kPairs = kItems / 2;
+            const uint32_t last = (hi - 1u) & ~1u;
+            typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+            u32x4 x[kPairs];
+#pragma unroll
+            for (int j = 0; j < kPairs; ++j) {
+                const uint32_t first = tile + uint32_t(j * kBlock + t) * 2u;
+                x[j] = *reinterpret_cast<const u32x4*>(src.kv + min(first, last));
+            }
+            // keep each load 16 bytes wide when the ids are not counted (the
+            // compiler would otherwise narrow it to the two key words)
+#pragma unroll
+            for (int j = 0; j < kPairs; ++j) asm volatile("" : "+v"(x[j]));
+#pragma unroll
+            for (int j = 0; j < kPairs; ++j) {
+                const uint32_t first = tile + uint32_t(j * kBlock + t) * 2u;
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    if (first + uint32_t(k) < hi) {
+                        const uint32_t kk = k ? x[j].w : x[j].y, vv = k ? x[j].z : x[j].x;
+                        atomicAdd(&h[w][digit_of(kk, shift)], 1u);
+                        if (IDS) atomicAdd(&hi_ids[IDS ? w : 0][vv >> id_shift], 1u);
+                    }
+                }
+            }
+            continue;
+        }
         K key[kItems];
         uint32_t val[kItems];
         // every load reads a valid element (the index is clamped to the
