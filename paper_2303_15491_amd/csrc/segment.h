@@ -572,10 +572,12 @@ __global__ __launch_bounds__(kBlock) void k_steepest(Fields F, uint32_t* up, uin
             }
 #pragma unroll
             for (int k = 0; k < kGroup; ++k) {
-                const uint32_t cross = own[k] | q[k], diff = own[k] ^ q[k];
-                const bool su = (cross & kExit) || (diff & 0xffffu) == 0u;
-                const bool sd = (cross & (kExit << 16)) || (diff >> 16) == 0u;
-                const uint32_t keep = (su ? 0x0000ffffu : 0u) | (sd ? 0xffff0000u : 0u);
+                // a half keeps its pointer when it or its target's pointer is
+                // an exit mark, else it takes the target's pointer (for a root
+                // target that is its own value again).  The exit bits (15 and
+                // 31) become the half masks by one 24-bit multiply.
+                const uint32_t cross = own[k] | q[k];
+                const uint32_t keep = ((cross >> 15) & 0x10001u) * 0xffffu;
                 const uint32_t nw = (own[k] & keep) | (q[k] & ~keep);
                 if (act[k] && nw != own[k]) {
                     lp[li[k]] = nw;  // each entry has one owner
