@@ -919,39 +919,61 @@ __global__ __launch_bounds__(kBlock) void k_rank_reduce(const uint64_t* keys,
     if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
-// rank_of_slot[vals[i]] = rank[i]; each thread ranks kItems consecutive items.
+// rank_of_slot[vals[i]] = rank[i].  A tile's keys are loaded coalesced into
+// LDS (one padding entry per 16, so that a thread's 16 consecutive entries
+// fall in different banks); each thread then scans its kItems consecutive
+// keys, puts the ranks back into LDS, and the ranks are stored by their
+// values in coalesced item order.
 __global__ __launch_bounds__(kBlock) void k_rank_apply(const uint64_t* keys, const uint32_t* vals,
                                                        const uint32_t* count_ptr,
                                                        const uint32_t* partial,
                                                        uint32_t* rank_of_slot) {
+    constexpr int kPad = kTile + kTile / 16;
+    __shared__ uint64_t sk[kPad];
+    __shared__ uint32_t sr[kPad];
     __shared__ uint32_t tmp[kWavesPerBlock];
+    auto pad = [](uint32_t i) { return i + (i >> 4); };
+    const uint32_t t = threadIdx.x;
     uint32_t lo, hi;
     worker_range(*count_ptr, blockIdx.x, gridDim.x, kTile, &lo, &hi);
     uint32_t run = partial[blockIdx.x];
     for (uint32_t tile = lo; tile < hi; tile += kTile) {
-        const uint32_t beg = tile + threadIdx.x * kItems;
+        const uint32_t tsize = min(uint32_t(kTile), hi - tile);
         uint64_t k[kItems];
         uint32_t v[kItems];
-        const uint64_t before = keys[beg ? min(beg, hi) - 1u : 0u];
 #pragma unroll
         for (int i = 0; i < kItems; ++i) {
-            const uint32_t idx = min(beg + uint32_t(i), hi - 1u);
+            const uint32_t idx = min(tile + uint32_t(i) * kBlock + t, hi - 1u);
             k[i] = keys[idx];
             v[i] = vals[idx];
         }
+        const uint64_t before = keys[tile ? tile - 1u : 0u];
+        __syncthreads();  // the previous tile's readers of sk and sr are done
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) sk[pad(uint32_t(i) * kBlock + t)] = k[i];
+        __syncthreads();
+        const uint32_t beg = t * kItems;
         uint32_t f[kItems], s = 0;
+        uint64_t prev = beg ? sk[pad(beg - 1u)] : before;
 #pragma unroll
         for (int i = 0; i < kItems; ++i) {
-            const uint64_t prev = i ? k[i - 1] : before;
-            f[i] = (beg + i < hi && (beg + i == 0 || k[i] != prev)) ? 1u : 0u;
+            const uint64_t cur = sk[pad(beg + uint32_t(i))];
+            f[i] = (beg + i < tsize && (tile + beg + i == 0 || cur != prev)) ? 1u : 0u;
             s += f[i];
+            prev = cur;
         }
         uint32_t tot;
         uint32_t r = run + block_exclusive_scan(s, tmp, &tot);
 #pragma unroll
         for (int i = 0; i < kItems; ++i) {
             r += f[i];
-            if (beg + i < hi) rank_of_slot[v[i]] = r - 1;
+            sr[pad(beg + uint32_t(i))] = r - 1u;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            const uint32_t j = uint32_t(i) * kBlock + t;
+            if (j < tsize) rank_of_slot[v[i]] = sr[pad(j)];
         }
         run += tot;
     }
