@@ -54,7 +54,7 @@ def algo_bytes(kind: str, invert: int):
 
 # Launch-shape knobs each kernel kind depends on (a traffic profile taken
 # with other values of these does not describe the kernel that ran).
-KIND_KNOBS = {"steepest": ("scan_depth", "scan_rounds"), "jump": ("scan_depth", "scan_rounds"),
+KIND_KNOBS = {"steepest": ("scan_depth", "scan_rounds", "packed_codes"), "jump": ("scan_depth", "scan_rounds"),
               "ms_final": ("scan_depth", "scan_rounds")}
 for _k in ("order_first", "order_scatter", "order_last", "order_regroup", "order_invert", "order_hist"):
     KIND_KNOBS[_k] = ("order_workers", "order_invert", "order_packed", "order_concurrent")

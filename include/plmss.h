@@ -256,6 +256,12 @@ const char* plmss_kernel_name(int32_t kind);
  *                              caller's stream, which then waits for the order
  *                              field; 0 (default) = everything on the caller's
  *                              stream, so that each kernel's time is its own.
+ *   PLMSS_TUNE_PACKED_CODES    neighbour scan over an order field of fewer
+ *                              than 2^28 vertices: 1 (default) = each rank
+ *                              shares one 32-bit word with a neighbour code
+ *                              and candidates are compared by plain max/min;
+ *                              0 = ranks and codes apart (the form used above
+ *                              that size).
  *   PLMSS_TUNE_SCAN_ROUNDS     in-tile path-compression sweeps of the
  *                              neighbour scan (1..8, default 3); what they
  *                              leave unfinished the cross-tile chase follows.
@@ -281,7 +287,8 @@ const char* plmss_kernel_name(int32_t kind);
 #define PLMSS_TUNE_ORDER_PACKED 5
 #define PLMSS_TUNE_SCAN_ROUNDS 6
 #define PLMSS_TUNE_ORDER_CONCURRENT 7
-#define PLMSS_TUNE_KNOBS 8
+#define PLMSS_TUNE_PACKED_CODES 8
+#define PLMSS_TUNE_KNOBS 9
 int32_t plmss_tune_set(int32_t knob, int64_t value);
 int64_t plmss_tune_get(int32_t knob);
 

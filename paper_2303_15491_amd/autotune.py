@@ -33,6 +33,7 @@ SPACE = {
     "order_packed": [1, 0],
     "scan_rounds": [3, 2, 4],
     "order_concurrent": [0, 1],  # not tuned by default: overlapping streams blur per-kernel times
+    "packed_codes": [1, 0],  # not tuned by default: the packed form is the faster one where it applies
     "sort_workers": [512, 256, 1024, 2048, 4096],
     "scan_depth": [8, 16, 32],
     "persist_blocks": [512, 1024, 2048, 4096, 8192, 16384],

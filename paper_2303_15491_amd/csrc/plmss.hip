@@ -35,10 +35,11 @@ constexpr KnobRange kKnobs[PLMSS_TUNE_KNOBS] = {
     {1, 1, 1, true, false},                    // ORDER_PACKED: 32-bit keys packed with ids
     {1, 8, kResolveRounds, false, false},      // SCAN_ROUNDS: in-tile jumping sweeps
     {1, 1, 0, true, false},                    // ORDER_CONCURRENT: order field on a second stream
+    {1, 1, 1, true, false},                    // PACKED_CODES: rank and code in one word when they fit
 };
 std::atomic<int64_t> g_knob[PLMSS_TUNE_KNOBS] = {kKnobs[0].def, kKnobs[1].def, kKnobs[2].def,
                                                  kKnobs[3].def, kKnobs[4].def, kKnobs[5].def,
-                                                 kKnobs[6].def, kKnobs[7].def};
+                                                 kKnobs[6].def, kKnobs[7].def, kKnobs[8].def};
 
 int64_t knob(int k) { return g_knob[k].load(std::memory_order_relaxed); }
 unsigned sort_workers() { return unsigned(knob(PLMSS_TUNE_SORT_WORKERS)); }
@@ -449,7 +450,8 @@ template <bool RESOLVE>
 void launch_steepest_any(int c, int zc, const Fields& F, unsigned grid, int32_t dtype, bool order,
                          uint32_t* up, uint32_t* dn, hipStream_t s) {
     // ranks of a field below 2^28 vertices leave four bits for the code
-    const bool packed = order && uint64_t(F.one.nx) * uint64_t(F.one.ny) * uint64_t(F.one.nz) < (1ull << 28);
+    const bool packed = order && knob(PLMSS_TUNE_PACKED_CODES) != 0 &&
+                        uint64_t(F.one.nx) * uint64_t(F.one.ny) * uint64_t(F.one.nz) < (1ull << 28);
     if (packed)
         launch_steepest_cls<RESOLVE, RankOrderPacked>(c, zc, F, grid, up, dn, s);
     else if (order)
