@@ -187,6 +187,48 @@ def per_kernel(launches, steps):
     return agg
 
 
+def bench_float64_copy(torch, plmss, lib, field32, ref, steps: int, warmup: int):
+    """The float64 copy of the same field (every value widened exactly): full
+    and labels-only step times, the per-kernel times of the full step, and a
+    check that every output equals the float32 run's."""
+    field = field32.double()
+    dims = plmss.dims_of(field.shape)
+    outs = {k: torch.empty(field.shape, dtype=torch.int32, device=field.device)
+            for k in ("asc", "desc", "ms", "order")}
+    outs["info"] = torch.zeros(4, dtype=torch.int32, device=field.device)
+    ws_bytes = lib.plmss_workspace_bytes(dims, plmss.F64, 1)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=field.device)
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    jobs = [plmss.Job(field.data_ptr(), dims, plmss.F64, outs["asc"].data_ptr(), outs["desc"].data_ptr(),
+                      outs["ms"].data_ptr(), outs["order"].data_ptr() if with_order else None,
+                      outs["info"].data_ptr()) for with_order in (True, False)]
+
+    def step(job):
+        rc = lib.plmss_segment(ctypes.byref(job), ctypes.c_void_p(ws.data_ptr()), ws_bytes, stream)
+        if rc:
+            raise plmss.PlmssError(rc, "plmss_segment")
+
+    for _ in range(warmup):
+        step(jobs[0])
+    torch.cuda.synchronize()
+    identical = all(torch.equal(outs[k], ref[k]) for k in ("asc", "desc", "ms", "order", "info"))
+    wall_full, _ = timed_region(lambda: step(jobs[0]), steps, torch)
+    wall_labels, _ = timed_region(lambda: step(jobs[1]), steps, torch)
+    max_launches = 128 * max(steps, 1)
+    trace = lib.plmss_trace_create(max_launches)
+    _, launches = timed_region(lambda: step(jobs[0]), steps, torch, lib, trace, max_launches)
+    lib.plmss_trace_destroy(trace)
+    n = field.numel()
+    del ws, outs, field
+    torch.cuda.empty_cache()
+    return {"ms_per_step": wall_full / steps, "value": n / (wall_full / steps * 1e-3) / 1e6,
+            "labels_only_ms_per_step": wall_labels / steps,
+            "labels_only_value": n / (wall_labels / steps * 1e-3) / 1e6, "unit": "Mvertices/s",
+            "identical_to_float32": identical,
+            "kernels_ms_per_step": {k: round(v["ms_per_step"], 4)
+                                    for k, v in sorted(per_kernel(launches, steps).items())}}
+
+
 def bench_batched(torch, plmss, steps: int, warmup: int):
     """The uneven batch (64 fields, sides 32..192): one plan launch (hipGraph)
     against a loop of plain per-field calls that reads each field's K as a
@@ -286,6 +328,7 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--knobs", default=None,
                     help='launch-shape knobs as JSON (e.g. {"scan_depth": 8}); skips the autotuner')
+    ap.add_argument("--no-float64", action="store_true", help="skip the float64 copy of the field")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device to device three times (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -423,6 +466,12 @@ def main():
                          f"{t1 - t0:.2f} s", "host_cpu": model, "host_nproc": ncpu}
 
     labels_value = n / (ms_step_l * 1e-3) / 1e6
+    f64 = None
+    if field.dtype == torch.float32 and not args.no_float64:
+        log("float64 copy of the field")
+        step_full()  # the outputs to compare against: the full path's
+        torch.cuda.synchronize()
+        f64 = bench_float64_copy(torch, plmss, lib, field, outs, steps=max(3, args.steps // 2), warmup=2)
     del ws, outs, field
     torch.cuda.empty_cache()
     batched = None if args.no_batched else bench_batched(torch, plmss, steps=max(3, args.steps // 2), warmup=2)
@@ -444,6 +493,7 @@ def main():
         "ms_per_step_labels_only_traced": wall_labels_traced / args.steps,
         "kernels_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in sorted(kern.items())},
         "kernels_ms_per_step_labels_only": {k: round(v["ms_per_step"], 4) for k, v in sorted(kern_l.items())},
+        "float64_copy": f64,
         "batched": batched,
         "serving": serving,
         "paper_context": "PLMSS Asc/Desc+MS on Miranda 512^3 (a different, simplified field): 57.6 Mvertices/s "
