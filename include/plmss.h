@@ -244,9 +244,12 @@ const char* plmss_kernel_name(int32_t kind);
  *                              w launches invert them, each for 1/w of the id
  *                              range.
  *   PLMSS_TUNE_ORDER_PACKED    1 (default) = 32-bit keys travel packed with
- *                              their ids in one 64-bit word until the last
- *                              pass, which reads them as two arrays; 0 = two
- *                              arrays throughout.
+ *                              their ids in one 64-bit word (split into two
+ *                              arrays for the last pass unless the inversion
+ *                              is by id chunks); 64-bit keys travel as a key
+ *                              array and an id array for their low four
+ *                              digits, then as their high half packed with
+ *                              the id; 0 = two arrays throughout.
  *   PLMSS_TUNE_ORDER_CONCURRENT  plmss_segment with an order field: 1 = the
  *                              order field is built on a
  *                              library-owned stream (one per device,

@@ -280,13 +280,6 @@ struct SplitItems {
     uint32_t* ids(int c) const { return vals[c ^ 1]; }
 };
 
-// Order field of a float field: an LSD radix sort of (key, id) with keys from
-// the values, then order[id] = position, written in one of three ways
-// (PLMSS_TUNE_ORDER_INVERT): fused into the last pass (scattered writes over
-// the whole order array); by id chunk (the last pass writes (id, position)
-// grouped by id range, k_chunk_partition regroups them by chunk of kChunk
-// ids, k_invert_chunks inverts each chunk in LDS); or as sorted ids inverted
-// by `windows` launches over parts of the id range.
 // Last pass of the order field and the inversion by id chunks: the last
 // pass writes (id, position) pairs grouped by id range to parts,
 // k_chunk_partition regroups them by chunk into parts2, k_invert_chunks
@@ -323,30 +316,31 @@ void invert_by_chunks(Src src, uint32_t n, unsigned workers, int last, uint64_t*
            [&] { k_invert_chunks<<<chunks, kInvertBlock, 0, s>>>(parts2, n, order); });
 }
 
-template <typename T, typename K, class Items>
-void sort_order_items(const T* f, uint32_t n, int32_t* order, const Work& w, int32_t* info, hipStream_t s,
-                      const Items& it) {
-    constexpr int passes = int(sizeof(K)) * 8 / kRadixBits;
+// The passes of an order sort after its first: middle passes at shifts
+// first_shift, first_shift + 8, ... below `last` over the items in buffer
+// cur, then the last pass at shift `last` and order[id] = position, written
+// in one of three ways (PLMSS_TUNE_ORDER_INVERT): fused into the last pass
+// (scattered writes over the whole order array); by id chunk (the last pass
+// writes (id, position) grouped by id range, k_chunk_partition regroups them
+// by chunk of kChunk ids, k_invert_chunks inverts each chunk in LDS); or as
+// sorted ids inverted by `windows` launches over parts of the id range.  K is
+// the key type of the items.
+template <typename K, class Items>
+void order_tail(const Items& it, int cur, int first_shift, int last, uint32_t n, unsigned workers,
+                int32_t* order, const Work& w, int32_t* info, hipStream_t s) {
     const unsigned tiles = unsigned(n_tiles(n));
-    const int64_t kw = knob(PLMSS_TUNE_ORDER_WORKERS);
-    const unsigned workers = kw == 0 ? tiles : unsigned(std::min<int64_t>(kw, tiles));
     const int64_t inv = knob(PLMSS_TUNE_ORDER_INVERT);
-    radix_pass(FieldSrc<T, K>{f}, it.dst(0), nullptr, n, workers, 0, true, w, info, s, kOrderKinds,
-               PLMSS_KERNEL_ORDER_FIRST);
-    int cur = 0;
-    for (int p = 1; p < passes - 1; ++p) {
+    for (int shift = first_shift; shift < last; shift += kRadixBits) {
         // the by-chunk inversion's histogram reads the ids with the keys, so
-        // the items stay packed to the end; the other inversions' histograms
-        // read only keys, which the pass before the last splits off
-        if (p == passes - 2 && inv != 1)
-            radix_pass(it.src(cur), it.split_dst(cur ^ 1), nullptr, n, workers, kRadixBits * p, false, w, info, s,
+        // the items stay as they are to the end; the other inversions'
+        // histograms read only keys, which the pass before the last splits off
+        if (shift + kRadixBits == last && inv != 1)
+            radix_pass(it.src(cur), it.split_dst(cur ^ 1), nullptr, n, workers, shift, false, w, info, s,
                        kOrderKinds);
         else
-            radix_pass(it.src(cur), it.dst(cur ^ 1), nullptr, n, workers, kRadixBits * p, false, w, info, s,
-                       kOrderKinds);
+            radix_pass(it.src(cur), it.dst(cur ^ 1), nullptr, n, workers, shift, false, w, info, s, kOrderKinds);
         cur ^= 1;
     }
-    const int last = kRadixBits * (passes - 1);
     if (inv == 1) {
         // the pairs go to it.spare(cur); it.own(cur) is free once the last
         // pass has read it
@@ -370,15 +364,57 @@ void sort_order_items(const T* f, uint32_t n, int32_t* order, const Work& w, int
     }
 }
 
+unsigned order_workers(uint32_t n) {
+    const unsigned tiles = unsigned(n_tiles(n));
+    const int64_t kw = knob(PLMSS_TUNE_ORDER_WORKERS);
+    return kw == 0 ? tiles : unsigned(std::min<int64_t>(kw, tiles));
+}
+
+// Order field of a float field: an LSD radix sort of (key, id) with keys from
+// the values (8-bit digits), then the inversion (order_tail).
+template <typename T, typename K, class Items>
+void sort_order_items(const T* f, uint32_t n, int32_t* order, const Work& w, int32_t* info, hipStream_t s,
+                      const Items& it) {
+    constexpr int passes = int(sizeof(K)) * 8 / kRadixBits;
+    const unsigned workers = order_workers(n);
+    radix_pass(FieldSrc<T, K>{f}, it.dst(0), nullptr, n, workers, 0, true, w, info, s, kOrderKinds,
+               PLMSS_KERNEL_ORDER_FIRST);
+    order_tail<K>(it, 0, kRadixBits, kRadixBits * (passes - 1), n, workers, order, w, info, s);
+}
+
+// 64-bit keys with packed items: the first four passes move (key, id) as a
+// key array and an id array; the fourth writes each key's high half packed
+// with its id in one word, and the last four passes sort those words like
+// 32-bit keys (8 bytes an item instead of 12).
+template <typename T>
+void sort_order_wide_packed(const T* f, uint32_t n, int32_t* order, const Work& w, int32_t* info,
+                            hipStream_t s) {
+    const unsigned workers = order_workers(n);
+    const SplitItems<uint64_t> sp{{reinterpret_cast<uint64_t*>(w.keys[0]), reinterpret_cast<uint64_t*>(w.keys[1])},
+                                  {w.vals[0], w.vals[1]}};
+    radix_pass(FieldSrc<T, uint64_t>{f}, sp.dst(0), nullptr, n, workers, 0, true, w, info, s, kOrderKinds,
+               PLMSS_KERNEL_ORDER_FIRST);
+    radix_pass(sp.src(0), sp.dst(1), nullptr, n, workers, kRadixBits, false, w, info, s, kOrderKinds);
+    radix_pass(sp.src(1), sp.dst(0), nullptr, n, workers, 2 * kRadixBits, false, w, info, s, kOrderKinds);
+    // keys[0]/vals[0] -> packed (high half, id) words in keys[1]
+    radix_pass(sp.src(0), HighPackedDst{reinterpret_cast<uint64_t*>(w.keys[1])}, nullptr, n, workers,
+               3 * kRadixBits, false, w, info, s, kOrderKinds);
+    const PackedItems pk{{reinterpret_cast<uint64_t*>(w.keys[1]), reinterpret_cast<uint64_t*>(w.keys[0])},
+                         w.vals[1], w.npad};
+    order_tail<uint32_t>(pk, 0, 0, 3 * kRadixBits, n, workers, order, w, info, s);
+}
+
 template <typename T, typename K>
 void sort_order(const T* f, uint32_t n, int32_t* order, const Work& w, int32_t* info, hipStream_t s) {
-    if constexpr (sizeof(K) == 4) {
-        if (knob(PLMSS_TUNE_ORDER_PACKED) != 0) {
+    if (knob(PLMSS_TUNE_ORDER_PACKED) != 0) {
+        if constexpr (sizeof(K) == 4) {
             const PackedItems it{{reinterpret_cast<uint64_t*>(w.keys[0]), reinterpret_cast<uint64_t*>(w.keys[1])},
                                  w.vals[1], w.npad};
             sort_order_items<T, K>(f, n, order, w, info, s, it);
-            return;
+        } else {
+            sort_order_wide_packed<T>(f, n, order, w, info, s);
         }
+        return;
     }
     const SplitItems<K> it{{reinterpret_cast<K*>(w.keys[0]), reinterpret_cast<K*>(w.keys[1])},
                            {w.vals[0], w.vals[1]}};

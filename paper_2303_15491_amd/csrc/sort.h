@@ -113,6 +113,15 @@ struct ArrayDst {
     }
 };
 
+// 64-bit keys whose low half is sorted: the high half packed with the id in
+// one word (key in the high word), for passes over PackedSrc.
+struct HighPackedDst {
+    uint64_t* kv;
+    __device__ __forceinline__ void put(uint32_t pos, uint64_t k, uint32_t v) const {
+        kv[pos] = (k & 0xffffffff00000000ull) | v;
+    }
+};
+
 // Final pass of the order field: the value is the vertex id, the position its
 // rank.
 template <typename K>

@@ -132,6 +132,25 @@ def test_float64_widened_is_identical(torch):
         assert torch.equal(a[k], b[k])
 
 
+@pytest.mark.parametrize("knobs", [
+    {"order_packed": 1, "order_invert": 1}, {"order_packed": 1, "order_invert": 0},
+    {"order_packed": 1, "order_invert": 3, "order_workers": 64}, {"order_packed": 0, "order_invert": 1},
+])
+def test_float64_order_field_knobs(torch, knobs):
+    """Float64 values that are not widened float32 (all 64 key bits carry
+    information, with ties and both signs) through every order-field layout."""
+    saved = plmss.tune_get()
+    try:
+        plmss.tune_set(**knobs)
+        rng = np.random.default_rng(17)
+        f = fields.smoothed_noise((30, 41, 67), 1.5, 11).astype(np.float64)
+        f += rng.standard_normal(f.shape) * 1e-12
+        f[rng.random(f.shape) < 0.01] = 0.25  # ties
+        _compare_full(torch, f, True, f"f64 knobs {knobs}")
+    finally:
+        plmss.tune_set(**saved)
+
+
 def test_nan_reported_on_device(torch):
     f = fields.smoothed_noise((8, 9, 10), 1.5, 3)
     f[3, 4, 5] = np.nan
