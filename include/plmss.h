@@ -206,7 +206,7 @@ int plmss_plan_launch_graph(plmss_plan* plan, void* workspace, size_t workspace_
 #define PLMSS_KERNEL_STEEPEST 4      /* steepest neighbours */
 #define PLMSS_KERNEL_JUMP 5          /* path compression (+ MS pair listing) */
 #define PLMSS_KERNEL_PREFIX 6        /* prefix sums */
-#define PLMSS_KERNEL_COMPACT 7       /* MS pair compaction */
+#define PLMSS_KERNEL_COMPACT 7       /* no longer launched (pairs are listed by the chase); the number stays reserved */
 #define PLMSS_KERNEL_RANK 8          /* MS pair ranking */
 #define PLMSS_KERNEL_MS_FINAL 9      /* MS id write-back */
 #define PLMSS_KERNEL_ORDER_HIST 10   /* order field: per-worker digit counts */

@@ -746,7 +746,7 @@ __global__ __launch_bounds__(kChaseBlock) void k_chase(Fields F, uint32_t* U, ui
             pd[i] = ok[i] ? pd[i] : (CHASE ? kMark : 0u);
         }
         if (CHASE) {
-            // the eight vertices of a thread advance together, so their
+            // the four vertices of a thread advance together, so their
             // gathers are in flight at the same time; from the second hop on,
             // a pointer is written back so that later readers jump further
             bool pending = true;

@@ -1,15 +1,17 @@
 // Stable least-significant-digit radix sort and device-wide prefix sums.
 //
-// Every pass is three launches over the same grid of "workers" (blocks); worker
-// b owns one contiguous slice of whole kTile-key tiles:
+// Every pass is a histogram and a scatter over the same grid of "workers"
+// (blocks, numbered XCD by XCD), with a digit scan between them; worker b
+// owns one contiguous slice of whole kTile-key tiles:
 //   hist    : per-worker digit counts            -> hist[digit][worker]
 //   scan    : exclusive scan of each digit's row -> hist (in place), dtotal
+//             (long rows are split over up to 16 blocks each)
 //   scatter : stable rank inside each tile, staged through LDS so that each
 //             digit's run leaves the block as one contiguous write, at
 //             digit base + hist[digit][worker] + rank
-// With a host-known length the grid has one worker per tile.  The length may
-// instead live in device memory (count_ptr) with a fixed grid, so a sort whose
-// size only the device knows needs no host round trip.
+// With a host-known length the grid can have one worker per tile.  The length
+// may instead live in device memory (count_ptr) with a fixed grid, so a sort
+// whose size only the device knows needs no host round trip.
 #pragma once
 
 #include "common.h"
@@ -448,8 +450,8 @@ __global__ __launch_bounds__(kBlock, sizeof(typename Src::key_t) == 4 ? 4 : 2) v
 // Last pass of the order field without a scattered write over the whole
 // order array: each key's sorted position comes from the same stable rank by
 // the top digit as in k_radix_scatter, and the pair (id, position) is then
-// written to one of 256 id ranges (id >> id_shift), so that k_invert_ranges
-// writes order[] one range at a time.  ihist/itotal: the per-worker id-range
+// written to one of at most 256 id ranges (id >> id_shift), from which
+// k_chunk_partition and k_invert_chunks write order[] one chunk at a time.  ihist/itotal: the per-worker id-range
 // counts and their totals (k_radix_hist with IDS, then the digit scan).
 template <class Src>
 __global__ __launch_bounds__(kBlock, 3) void k_rank_partition(Src src, uint32_t n, int shift,
