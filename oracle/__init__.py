@@ -60,9 +60,12 @@ def _load():
         lib.plmss_oracle_degree_sum.argtypes = [i64, i64, i64]
         lib.plmss_oracle_degree_sum.restype = ctypes.c_int64
         lib.plmss_oracle_neighbours.argtypes = [i64, i64, i64, i64, vp]
+        lib.plmss_oracle_marching_rows.argtypes = [i64, i64, i64]
+        lib.plmss_oracle_marching_rows.restype = ctypes.c_int64
+        lib.plmss_oracle_marching.argtypes = [vp, i64, i64, i64, ctypes.c_int, vp, vp]
         for name in ("plmss_oracle_order", "plmss_oracle_steepest", "plmss_oracle_labels",
                      "plmss_oracle_ms", "plmss_oracle_segment", "plmss_oracle_trace",
-                     "plmss_oracle_neighbours"):
+                     "plmss_oracle_neighbours", "plmss_oracle_marching"):
             getattr(lib, name).restype = ctypes.c_int
         del i32p, i64p
         _lib = lib
@@ -196,3 +199,25 @@ def neighbours(nx: int, ny: int, nz: int, v: int):
     if k < 0:
         raise OracleError(k, "neighbours")
     return sorted(int(a) for a in nb[:k])
+
+
+def marching(labels: np.ndarray, mode: int = 0, with_codes: bool = True) -> dict:
+    """Multi-label marching index (Sec. "Multi-Label Marching
+    Triangles/Tetrahedra") of an int32 label field: per-cell codes (uint8,
+    cell ((row * (nx-1)) + x) * cells_per_cube + t), row_offsets (int64,
+    rows + 1 entries, exclusive prefix of the output primitives per row, the
+    last entry the total) and total.  mode 0: region separators, 1: region
+    boundaries."""
+    labels = np.ascontiguousarray(labels, dtype=np.int32)
+    nx, ny, nz = _dims(labels)
+    lib = _load()
+    rows = int(lib.plmss_oracle_marching_rows(nx, ny, nz))
+    per = 6 if nz > 1 else 2
+    codes = np.zeros(rows * (nx - 1) * per if rows else 0, np.uint8)
+    offsets = np.zeros(rows + 1, np.int64)
+    rc = lib.plmss_oracle_marching(_p(labels), nx, ny, nz, int(mode), _p(codes) if with_codes and rows else None,
+                                   _p(offsets))
+    if rc:
+        raise OracleError(rc, "marching")
+    return {"codes": codes if with_codes else None, "row_offsets": offsets, "total": int(offsets[-1]),
+            "rows": rows, "cells_per_cube": per}

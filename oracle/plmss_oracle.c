@@ -370,3 +370,101 @@ int plmss_oracle_neighbours(int64_t nx, int64_t ny, int64_t nz, int64_t v, int64
     if (!nb || v < 0 || v >= g.n) return ORC_E_ARG;
     return neighbours(&g, v, nb);
 }
+
+/* ---- multi-label marching index (Sec. "Multi-Label Marching
+ * Triangles/Tetrahedra") --------------------------------------------------
+ *
+ * Cells: in 3-D (nx, ny, nz all > 1) the six Kuhn tetrahedra of every cube;
+ * in 2-D (nz == 1 and nx, ny > 1) the two triangles of every square; no
+ * cells otherwise.  A cell's vertices, in increasing id order, are the cube's
+ * low corner, then one, two (and in 3-D three) unit steps along the axes in
+ * the order given by the cell's permutation: 3-D permutations (x,y,z),
+ * (x,z,y), (y,x,z), (y,z,x), (z,x,y), (z,y,x) are tetrahedra 0..5; 2-D
+ * (x,y), (y,x) are triangles 0, 1.  Cell index: ((row * (nx-1)) + x) *
+ * cells_per_cube + t, rows being the (y, z) rows of cubes (z-major), or the
+ * y rows of squares in 2-D.
+ *
+ * The local label of a cell's i-th vertex is the index of the first vertex
+ * (in that order) that carries the same label: a is always 0, b is 0 or 1,
+ * c is 0, 1 or 2, d is 0..3, as in the paper's table of tetrahedron codes.
+ * The code is (b << 4) | (c << 2) | d for a tetrahedron and (b << 2) | c for
+ * a triangle.
+ *
+ * Output per cell (mode 0, region separators): the number of separating
+ * triangles (3-D) or edges (2-D) of the paper's case figures: by the number
+ * of distinct labels at the cell's vertices, 3-D: 1 -> 0, 2 -> 1 when one
+ * vertex stands alone and 2 when the labels split two and two, 3 -> 5,
+ * 4 -> 12; 2-D: 1 -> 0, 2 -> 1, 3 -> 3.  Mode 1 (region boundaries): one
+ * triangle for a tetrahedron with exactly three vertices of one label and one
+ * edge for a triangle with exactly two; zero otherwise.
+ *
+ * row_offsets[r] = number of output primitives of rows before r, and
+ * row_offsets[rows] = the total.  codes may be NULL.
+ */
+int64_t plmss_oracle_marching_rows(int64_t nx, int64_t ny, int64_t nz) {
+    if (nx > 1 && ny > 1 && nz > 1) return (ny - 1) * (nz - 1);
+    if (nz == 1 && nx > 1 && ny > 1) return ny - 1;
+    return 0;
+}
+
+static const int PERM3[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+static const int PERM2[2][2] = {{0, 1}, {1, 0}};
+
+int plmss_oracle_marching(const int32_t* labels, int64_t nx, int64_t ny, int64_t nz, int mode,
+                          uint8_t* codes, int64_t* row_offsets) {
+    if (!labels || !row_offsets || nx < 1 || ny < 1 || nz < 1 || (mode != 0 && mode != 1)) return ORC_E_ARG;
+    const int64_t rows = plmss_oracle_marching_rows(nx, ny, nz);
+    const int three_d = nz > 1;
+    const int nv = three_d ? 4 : 3, ncells = three_d ? 6 : 2;
+    int64_t total = 0;
+    for (int64_t r = 0; r < rows; ++r) {
+        row_offsets[r] = total;
+        const int64_t y = three_d ? r % (ny - 1) : r, z = three_d ? r / (ny - 1) : 0;
+        for (int64_t x = 0; x + 1 < nx; ++x) {
+            for (int t = 0; t < ncells; ++t) {
+                int32_t lab[4];
+                int64_t p[3] = {x, y, z};
+                lab[0] = labels[p[0] + nx * (p[1] + ny * p[2])];
+                for (int i = 1; i < nv; ++i) {
+                    const int axis = three_d ? PERM3[t][i - 1] : PERM2[t][i - 1];
+                    p[axis] += 1;
+                    lab[i] = labels[p[0] + nx * (p[1] + ny * p[2])];
+                }
+                int local[4], distinct = 0, size[4] = {0, 0, 0, 0};
+                for (int i = 0; i < nv; ++i) {
+                    int j = 0;
+                    while (lab[j] != lab[i]) ++j;
+                    local[i] = j;
+                    if (j == i) ++distinct;
+                    size[j] += 1;
+                }
+                int count;
+                if (mode == 0) {
+                    if (three_d) {
+                        if (distinct == 1) count = 0;
+                        else if (distinct == 2) {
+                            int alone = 0;
+                            for (int i = 0; i < 4; ++i) alone |= size[i] == 1;
+                            count = alone ? 1 : 2;
+                        } else if (distinct == 3) count = 5;
+                        else count = 12;
+                    } else {
+                        count = distinct == 1 ? 0 : distinct == 2 ? 1 : 3;
+                    }
+                } else {
+                    int big = 0;
+                    for (int i = 0; i < nv; ++i) big |= size[i] == nv - 1;
+                    count = (distinct == 2 && big) ? 1 : 0;
+                }
+                total += count;
+                if (codes) {
+                    const int code = three_d ? (local[1] << 4) | (local[2] << 2) | local[3]
+                                             : (local[1] << 2) | local[2];
+                    codes[(r * (nx - 1) + x) * ncells + t] = (uint8_t)code;
+                }
+            }
+        }
+    }
+    row_offsets[rows] = total;
+    return ORC_OK;
+}
