@@ -229,6 +229,66 @@ def bench_float64_copy(torch, plmss, lib, field32, ref, steps: int, warmup: int)
                                     for k, v in sorted(per_kernel(launches, steps).items())}}
 
 
+def bench_marching(torch, plmss, lib, labels, steps: int, warmup: int, cpu_planes: int):
+    """The multi-label marching index over the MS labels of the field: time
+    per call with and without per-cell codes (region separators), the
+    per-launch time of the count kernel against the HBM roofline of its
+    algorithmic bytes (labels read once, codes written once, one offset per
+    row), and the oracle on a slab of the same labels."""
+    dims = plmss.dims_of(labels.shape)
+    rows = int(lib.plmss_marching_rows(dims))
+    cubes = rows * (int(dims.nx) - 1)
+    per = 6 if dims.nz > 1 else 2
+    codes = torch.empty(max(cubes * per, 2), dtype=torch.uint8, device=labels.device)
+    offs = torch.empty(rows + 1, dtype=torch.int64, device=labels.device)
+    ws_bytes = lib.plmss_marching_workspace_bytes(dims)
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=labels.device)
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    res = {"rows": rows, "cells": cubes * per}
+    for with_codes in (True, False):
+        cptr = ctypes.c_void_p(codes.data_ptr()) if with_codes else None
+
+        def step():
+            rc = lib.plmss_marching_index(ctypes.c_void_p(labels.data_ptr()), dims, plmss.MARCH_SEPARATORS, cptr,
+                                          ctypes.c_void_p(offs.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                                          ws_bytes, stream)
+            if rc:
+                raise plmss.PlmssError(rc, "plmss_marching_index")
+
+        for _ in range(warmup):
+            step()
+        wall, _ = timed_region(step, steps, torch)
+        max_launches = 8 * steps
+        trace = lib.plmss_trace_create(max_launches)
+        _, launches = timed_region(step, steps, torch, lib, trace, max_launches)
+        lib.plmss_trace_destroy(trace)
+        kern = per_kernel(launches, steps)
+        avg = kern["march_count"]["avg_launch_ms"]
+        nbytes = 4.0 * labels.numel() + (per * cubes if with_codes else 0) + 8.0 * rows
+        key = "with_codes" if with_codes else "counts_only"
+        res[key] = {"ms_per_call": wall / steps, "value": labels.numel() / (wall / steps * 1e-3) / 1e6,
+                    "unit": "Mvertices/s", "count_kernel_avg_launch_ms": avg,
+                    "algorithmic_bytes_per_launch": nbytes,
+                    "basis": f"4 B/vertex labels read{f' + {per} B/cube codes written' if with_codes else ''}"
+                             f" + 8 B/row offsets",
+                    "achieved_gbs": nbytes / (avg * 1e-3) / 1e9,
+                    "frac": nbytes / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    "kernels_ms_per_call": {k: round(v["ms_per_step"], 4) for k, v in sorted(kern.items())}}
+    res["total_separators"] = int(offs[-1].item())
+    if cpu_planes > 0:
+        import oracle
+
+        sl = np.ascontiguousarray(labels[:cpu_planes].cpu().numpy())
+        t0 = time.perf_counter()
+        oracle.marching(sl, 0)
+        t1 = time.perf_counter()
+        res["cpu_baseline"] = {"value": sl.size / (t1 - t0) / 1e6, "unit": "Mvertices/s", "cores": 1,
+                               "kind": "oracle", "sample": f"serial C oracle with codes on {tuple(sl.shape)}, "
+                                                           f"{t1 - t0:.2f} s"}
+    del codes, offs, ws
+    return res
+
+
 def bench_batched(torch, plmss, steps: int, warmup: int):
     """The uneven batch (64 fields, sides 32..192): one plan launch (hipGraph)
     against a loop of plain per-field calls that reads each field's K as a
@@ -329,6 +389,7 @@ def main():
     ap.add_argument("--knobs", default=None,
                     help='launch-shape knobs as JSON (e.g. {"scan_depth": 8}); skips the autotuner')
     ap.add_argument("--no-float64", action="store_true", help="skip the float64 copy of the field")
+    ap.add_argument("--no-marching", action="store_true", help="skip the marching index over the MS labels")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device to device three times (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -472,6 +533,13 @@ def main():
         step_full()  # the outputs to compare against: the full path's
         torch.cuda.synchronize()
         f64 = bench_float64_copy(torch, plmss, lib, field, outs, steps=max(3, args.steps // 2), warmup=2)
+    marching = None
+    if not args.no_marching and field.ndim >= 2:
+        log("marching index over the MS labels")
+        step_full()
+        torch.cuda.synchronize()
+        marching = bench_marching(torch, plmss, lib, outs["ms"], steps=args.steps, warmup=2,
+                                  cpu_planes=args.cpu_slab if field.ndim == 3 else 0)
     del ws, outs, field
     torch.cuda.empty_cache()
     batched = None if args.no_batched else bench_batched(torch, plmss, steps=max(3, args.steps // 2), warmup=2)
@@ -494,6 +562,7 @@ def main():
         "kernels_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in sorted(kern.items())},
         "kernels_ms_per_step_labels_only": {k: round(v["ms_per_step"], 4) for k, v in sorted(kern_l.items())},
         "float64_copy": f64,
+        "marching_index": marching,
         "batched": batched,
         "serving": serving,
         "paper_context": "PLMSS Asc/Desc+MS on Miranda 512^3 (a different, simplified field): 57.6 Mvertices/s "

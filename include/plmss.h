@@ -143,6 +143,54 @@ int plmss_ms_ids(const int32_t* asc, const int32_t* desc, int64_t n, int32_t* ms
                  void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * Multi-label marching index (paper, Sec. "Multi-Label Marching
+ * Triangles/Tetrahedra", Table of tetrahedron binary codes and the figure of
+ * its case triangulations): the first pass of a geometry extraction over a
+ * label field (MS, ascending or descending labels).  Nothing is triangulated
+ * here; the pass says, for every cell, which labelling case it is in and how
+ * many primitives it will emit, and where each row's primitives start.
+ *
+ * Cells.  3-D grids (nx, ny, nz > 1): the six tetrahedra of every cube along
+ * its (1,1,1) diagonal (the triangulation of the neighbour scan); 2-D grids
+ * (nz == 1, nx, ny > 1): the two triangles of every square along its (1,1)
+ * diagonal; other grids have no cells.  A cell's vertices, in increasing id
+ * order, are the cube's low corner (x, y, z) followed by one, two (three) unit
+ * steps along the axes in the order of the cell's permutation: tetrahedra
+ * 0..5 step (x,y,z), (x,z,y), (y,x,z), (y,z,x), (z,x,y), (z,y,x); triangles
+ * 0, 1 step (x,y), (y,x).  Rows of cells are the (y, z) rows of cubes in
+ * z-major order ((ny-1)(nz-1) rows of nx-1 cubes) or the y rows of squares
+ * (ny-1 rows); plmss_marching_rows returns that number (0 for grids without
+ * cells, -1 for invalid dims).
+ *
+ * codes (device uint8, nullable, 2-byte aligned): byte
+ * (row * (nx-1) + x) * C + t, C = 6 (tetrahedra) or 2 (triangles), holds cell
+ * t's code: with the local label of a vertex being the index of the first of
+ * the cell's vertices that carries its label, code = b << 4 | c << 2 | d for
+ * a tetrahedron (a, b, c, d), b << 2 | c for a triangle (a, b, c).
+ *
+ * mode PLMSS_MARCH_SEPARATORS counts the separating primitives of the case
+ * figures: tetrahedra with 1 label 0, with 2 labels 1 (one vertex apart) or 2
+ * (two and two), 3 labels 5, 4 labels 12 triangles; triangles with 1, 2, 3
+ * labels 0, 1, 3 edges.  PLMSS_MARCH_BOUNDARIES counts one triangle per
+ * tetrahedron with exactly three vertices of one label and one edge per
+ * triangle with exactly two labels (the boundary surface of the
+ * single-label variant).
+ *
+ * row_offsets (device uint64[rows + 1], out): row_offsets[r] = primitives of
+ * rows before r; row_offsets[rows] = the total.
+ * labels: device int32[N] in the field's layout (any values).  Workspace:
+ * plmss_marching_workspace_bytes(dims) bytes, 256-byte aligned.
+ * Returns PLMSS_OK, PLMSS_E_ARG (NULL labels/row_offsets, odd codes address,
+ * bad mode), PLMSS_E_DIMS, PLMSS_E_TOO_LARGE, PLMSS_E_WORKSPACE or PLMSS_E_HIP.
+ */
+#define PLMSS_MARCH_SEPARATORS 0
+#define PLMSS_MARCH_BOUNDARIES 1
+int64_t plmss_marching_rows(plmss_dims dims);
+size_t plmss_marching_workspace_bytes(plmss_dims dims);
+int plmss_marching_index(const int32_t* labels, plmss_dims dims, int32_t mode, uint8_t* codes,
+                         uint64_t* row_offsets, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
  * Many fields of different sizes in one pass: the same results as calling
  * plmss_segment on each job, computed by one launch per step over all fields
  * together.  jobs is a HOST array of n_jobs entries; the sum of their N must
@@ -215,7 +263,8 @@ int plmss_plan_launch_graph(plmss_plan* plan, void* workspace, size_t workspace_
 #define PLMSS_KERNEL_ORDER_FIRST 13  /* order field: first pass, field to (key, id) */
 #define PLMSS_KERNEL_ORDER_LAST 14   /* order field: last pass (sorted ids, or (id, position) by range) */
 #define PLMSS_KERNEL_ORDER_REGROUP 15 /* order field: (id, position) regrouped by id chunk */
-#define PLMSS_KERNEL_KINDS 16
+#define PLMSS_KERNEL_MARCH 16      /* marching index: cell codes and row counts */
+#define PLMSS_KERNEL_KINDS 17
 
 typedef struct plmss_trace plmss_trace;
 plmss_trace* plmss_trace_create(int32_t max_launches);

@@ -15,13 +15,15 @@ import os
 
 __all__ = ["PlmssError", "library", "segment", "order_field", "steepest", "compress", "ms_ids",
            "segment_batch", "workspace_bytes", "batch_workspace_bytes", "batch_needs", "Plan",
-           "tune_get", "tune_set", "KNOBS"]
+           "tune_get", "tune_set", "KNOBS", "marching_rows", "marching_index", "MARCH_SEPARATORS",
+           "MARCH_BOUNDARIES"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libplmss.so")
 
 OK, E_ARG, E_DIMS, E_TOO_LARGE, E_NAN, E_WORKSPACE, E_HIP = 0, -1, -2, -3, -4, -5, -6
 F32, F64 = 0, 1
+MARCH_SEPARATORS, MARCH_BOUNDARIES = 0, 1
 
 
 class PlmssError(RuntimeError):
@@ -57,6 +59,10 @@ _SIGNATURES = {
     "plmss_ms_workspace_bytes": ([ctypes.c_int64], ctypes.c_size_t),
     "plmss_ms_ids": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                       ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
+    "plmss_marching_rows": ([Dims], ctypes.c_int64),
+    "plmss_marching_workspace_bytes": ([Dims], ctypes.c_size_t),
+    "plmss_marching_index": ([ctypes.c_void_p, Dims, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                              ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
     "plmss_batch_workspace_bytes": ([ctypes.c_int32, ctypes.POINTER(Job)], ctypes.c_size_t),
     "plmss_segment_batch": ([ctypes.c_int32, ctypes.POINTER(Job), ctypes.c_void_p, ctypes.c_size_t,
                              ctypes.c_void_p], ctypes.c_int),
@@ -277,6 +283,48 @@ def ms_ids(asc, desc, workspace=None, stream=None):
     _check(lib.plmss_ms_ids(_ptr(asc), _ptr(desc), n, _ptr(ms), _ptr(info), _ptr(ws), ws.numel(),
                             _stream(stream)), "plmss_ms_ids")
     return ms, info
+
+
+def marching_rows(shape) -> int:
+    """Rows of cells of a grid: (ny-1)(nz-1) rows of cubes, ny-1 rows of
+    squares for nz == 1, 0 for grids without cells."""
+    return int(library().plmss_marching_rows(dims_of(shape)))
+
+
+def marching_index(labels, mode: int = MARCH_SEPARATORS, with_codes: bool = False, workspace=None,
+                   stream=None, out=None):
+    """Multi-label marching index of an int32 device label field.
+
+    Returns ``(codes, row_offsets)``: ``codes`` a uint8 device tensor of
+    rows * (nx-1) * C cell codes (C = 6 tetrahedra per cube, 2 triangles per
+    square), or None without ``with_codes``; ``row_offsets`` an int64 device
+    tensor of rows + 1 exclusive primitive offsets, the last being the total.
+    ``mode`` is MARCH_SEPARATORS or MARCH_BOUNDARIES.  ``out`` may pass
+    ``(codes, row_offsets)`` tensors to fill.
+    """
+    torch = _torch()
+    if not labels.is_cuda or not labels.is_contiguous() or labels.dtype != torch.int32:
+        raise ValueError("labels must be a contiguous int32 device tensor")
+    dims = dims_of(labels.shape)
+    lib = library()
+    rows = int(lib.plmss_marching_rows(dims))
+    if rows < 0:
+        raise PlmssError(E_DIMS, "plmss_marching_rows")
+    cells = rows * max(int(dims.nx) - 1, 0) * (6 if dims.nz > 1 else 2)
+    if out is not None:
+        codes, offs = out
+        if offs.dtype != torch.int64 or offs.numel() < rows + 1 or not offs.is_contiguous():
+            raise ValueError("row_offsets must be a contiguous int64 tensor of rows + 1 entries")
+        if codes is not None and (codes.dtype != torch.uint8 or codes.numel() < cells
+                                  or not codes.is_contiguous()):
+            raise ValueError("codes must be a contiguous uint8 tensor of one byte per cell")
+    else:
+        offs = torch.empty(rows + 1, dtype=torch.int64, device=labels.device)
+        codes = torch.empty(max(cells, 1), dtype=torch.uint8, device=labels.device) if with_codes else None
+    ws = _workspace(lib.plmss_marching_workspace_bytes(dims), labels.device, workspace)
+    _check(lib.plmss_marching_index(_ptr(labels), dims, int(mode), _ptr(codes), _ptr(offs), _ptr(ws), ws.numel(),
+                                    _stream(stream)), "plmss_marching_index")
+    return (codes[:cells] if codes is not None else None), offs
 
 
 def _jobs(fields, outs):

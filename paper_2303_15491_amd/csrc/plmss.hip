@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "common.h"
+#include "marching.h"
 #include "segment.h"
 #include "sort.h"
 
@@ -172,6 +173,20 @@ bool ws_ok(const void* ws, size_t have, size_t need) {
 int launch_status() { return hipGetLastError() == hipSuccess ? PLMSS_OK : PLMSS_E_HIP; }
 
 unsigned grid_for(uint64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
+
+// ---- marching index sizes -------------------------------------------------------------------
+// Rows of cells: the (y, z) rows of cubes of a 3-D grid, the y rows of squares
+// of a 2-D one (nz == 1), none for lines and for grids one vertex thick.
+int64_t march_rows(const plmss_dims& d) {
+    if (d.nx > 1 && d.ny > 1 && d.nz > 1) return (d.ny - 1) * (d.nz - 1);
+    if (d.nz == 1 && d.nx > 1 && d.ny > 1) return d.ny - 1;
+    return 0;
+}
+
+// One u64 per count block (its sum, then its first offset).
+size_t march_ws_bytes(uint64_t rows) {
+    return align_up(8 * std::max<uint64_t>(1, (rows + kMarchRowsPerBlock - 1) / kMarchRowsPerBlock), 256);
+}
 
 // ---- optional launch tracing -------------------------------------------------------------
 // While a trace is active on the calling host thread, every kernel launch is
@@ -921,6 +936,59 @@ int plmss_ms_ids(const int32_t* asc, const int32_t* desc, int64_t n, int32_t* ms
     return launch_status();
 }
 
+int64_t plmss_marching_rows(plmss_dims dims) {
+    uint64_t n;
+    if (check_dims(dims, &n) != PLMSS_OK) return -1;
+    return march_rows(dims);
+}
+
+size_t plmss_marching_workspace_bytes(plmss_dims dims) {
+    uint64_t n;
+    if (check_dims(dims, &n) != PLMSS_OK) return 0;
+    return march_ws_bytes(uint64_t(march_rows(dims)));
+}
+
+int plmss_marching_index(const int32_t* labels, plmss_dims dims, int32_t mode, uint8_t* codes,
+                         uint64_t* row_offsets, void* workspace, size_t workspace_bytes, void* stream) {
+    if (!labels || !row_offsets || (mode != PLMSS_MARCH_SEPARATORS && mode != PLMSS_MARCH_BOUNDARIES))
+        return PLMSS_E_ARG;
+    if (codes && (reinterpret_cast<uintptr_t>(codes) & 1u)) return PLMSS_E_ARG;
+    uint64_t n;
+    const int rc = check_dims(dims, &n);
+    if (rc != PLMSS_OK) return rc;
+    const uint64_t rows = uint64_t(march_rows(dims));
+    if (!ws_ok(workspace, workspace_bytes, march_ws_bytes(rows))) return PLMSS_E_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint64_t* block_sums = static_cast<uint64_t*>(workspace);
+    const unsigned blocks = unsigned((rows + kMarchRowsPerBlock - 1) / kMarchRowsPerBlock);
+    const int nx = int(dims.nx), ny = int(dims.ny);
+    if (rows > 0)
+        launch(PLMSS_KERNEL_MARCH, s, [&] {
+            const int shape = (dims.nz > 1 ? 4 : 0) | (mode ? 2 : 0) | (codes ? 1 : 0);
+            auto go = [&](auto kernel) {
+                kernel<<<blocks, kBlock, 0, s>>>(labels, nx, ny, uint32_t(rows), codes, row_offsets, block_sums);
+            };
+            switch (shape) {
+                case 0: go(k_march_count<false, 0, false>); break;
+                case 1: go(k_march_count<false, 0, true>); break;
+                case 2: go(k_march_count<false, 1, false>); break;
+                case 3: go(k_march_count<false, 1, true>); break;
+                case 4: go(k_march_count<true, 0, false>); break;
+                case 5: go(k_march_count<true, 0, true>); break;
+                case 6: go(k_march_count<true, 1, false>); break;
+                default: go(k_march_count<true, 1, true>); break;
+            }
+        });
+    launch(PLMSS_KERNEL_PREFIX, s, [&] {
+        k_march_scan_blocks<<<1, kBlock, 0, s>>>(block_sums, blocks, row_offsets + rows);
+    });
+    if (rows > 0)
+        launch(PLMSS_KERNEL_PREFIX, s, [&] {
+            k_march_offsets<<<blocks, kBlock, 0, s>>>(row_offsets, uint32_t(rows), block_sums);
+        });
+    return launch_status();
+}
+
 size_t plmss_batch_workspace_bytes(int32_t n_jobs, const plmss_job* jobs) {
     BatchLayout B;
     if (batch_layout(n_jobs, jobs, scan_depth(), &B) != PLMSS_OK) return 0;
@@ -1154,7 +1222,7 @@ const char* plmss_kernel_name(int32_t kind) {
     static const char* names[PLMSS_KERNEL_KINDS] = {
         "misc", "radix_hist", "radix_digit_scan", "radix_scatter", "steepest", "jump", "prefix_sum",
         "pair_compact", "pair_rank", "ms_final", "order_hist", "order_scatter", "order_invert",
-        "order_first", "order_last", "order_regroup"};
+        "order_first", "order_last", "order_regroup", "march_count"};
     return (kind >= 0 && kind < PLMSS_KERNEL_KINDS) ? names[kind] : "unknown";
 }
 

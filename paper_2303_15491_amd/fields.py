@@ -18,6 +18,10 @@ Rayleigh-Taylor "Miranda"), which are not used: only their shapes are kept.
   noise, one member of the uneven batch.
 * ``batch_shapes`` / ``batch_fields`` -- the 64-field uneven batch.
 * ``serving_trace``    -- Poisson arrivals of mixed 2-D and 3-D requests.
+* ``random_labels``    -- int32 labels drawn uniformly from {0..k-1}.
+* ``region_labels``    -- piecewise-constant int32 labels of warped boxes with
+  salt, the shape of a segmentation's label field (inputs of the marching
+  index at sizes the oracle cannot segment in a test).
 """
 from __future__ import annotations
 
@@ -119,6 +123,48 @@ def serving_trace(count: int, seed: int = 5, rate: float = 200.0):
         out.append({"t": t, "shape": shape, "sigma": float(rng.uniform(1.5, 4.0)),
                     "seed": int(rng.integers(0, 2**31 - 1))})
     return out
+
+
+def random_labels(shape, k: int, seed: int) -> np.ndarray:
+    """int32 labels drawn uniformly from {0..k-1} (PCG64)."""
+    return _rng(seed).integers(0, k, size=tuple(shape), dtype=np.int32)
+
+
+def region_labels(shape, seed: int, cell: float = 6.0, warp: float = 2.5, salt: float = 1e-3) -> np.ndarray:
+    """Piecewise-constant int32 labels: each vertex takes the id of the box of
+    side ``cell`` that holds it after every coordinate is shifted by a smooth
+    warp of the other coordinates (warp * sin(2 pi (f1 u / n_u + f2 v / n_v) +
+    phase), f ~ U{1..3}), so that region boundaries are curved surfaces; box
+    ids are hashed to spread them over [0, 2^31).  Then a fraction ``salt`` of
+    the vertices (drawn with repetition) get ids of their own, which adds
+    cells with three and four labels."""
+    rng = _rng(seed)
+    shape = tuple(int(s) for s in shape)
+    nd = len(shape)
+    key = np.zeros(shape, np.uint32)
+    for a in range(nd):
+        others = [b for b in range(nd) if b != a]
+        w = np.zeros([shape[b] if b != a else 1 for b in range(nd)], np.float32)
+        if others:
+            f = rng.integers(1, 4, size=len(others))
+            phase = rng.uniform(0, 2 * np.pi)
+            arg = np.full(w.shape, phase, np.float64)
+            for fb, b in zip(f, others):
+                t = np.arange(shape[b], dtype=np.float64) * (2 * np.pi * fb / shape[b])
+                arg = arg + t.reshape([shape[b] if c == b else 1 for c in range(nd)])
+            w = (warp * np.sin(arg)).astype(np.float32)
+        c = np.arange(shape[a], dtype=np.float32).reshape([shape[a] if b == a else 1 for b in range(nd)])
+        q = np.floor((c + w) / np.float32(cell)).astype(np.int32) + 16
+        key *= np.uint32(1000003)
+        key += q.astype(np.uint32)
+    key *= np.uint32(2654435761)
+    lab = (key >> np.uint32(1)).astype(np.int32)
+    n = lab.size
+    m = int(salt * n)
+    if m:
+        idx = rng.integers(0, n, size=m)
+        lab.reshape(-1)[idx] = rng.integers(0, 2**31 - 1, size=m, dtype=np.int32)
+    return lab
 
 
 # The named workloads.

@@ -124,3 +124,32 @@ def test_tuning_knobs_validate_ranges():
             plmss.tune_set(nothing=1)
     finally:
         plmss.tune_set(**saved)
+
+
+def test_marching_argument_errors_and_rows():
+    import oracle
+
+    orc_rows = oracle._load().plmss_oracle_marching_rows
+    lib = plmss.library()
+    d = plmss.Dims(8, 8, 8)
+    ws = lib.plmss_marching_workspace_bytes(d)
+    assert ws >= 8 and ws % 256 == 0
+    mi = lib.plmss_marching_index
+    assert mi(None, d, 0, None, FAKE, FAKE, ws, None) == plmss.E_ARG
+    assert mi(FAKE, d, 0, None, None, FAKE, ws, None) == plmss.E_ARG
+    assert mi(FAKE, d, 2, None, FAKE, FAKE, ws, None) == plmss.E_ARG
+    assert mi(FAKE, d, -1, None, FAKE, FAKE, ws, None) == plmss.E_ARG
+    assert mi(FAKE, d, 0, FAKE + 1, FAKE, FAKE, ws, None) == plmss.E_ARG  # odd codes address
+    assert mi(FAKE, plmss.Dims(0, 8, 8), 0, None, FAKE, FAKE, ws, None) == plmss.E_DIMS
+    assert mi(FAKE, plmss.Dims(2048, 2048, 512), 0, None, FAKE, FAKE, ws, None) == plmss.E_TOO_LARGE
+    assert mi(FAKE, d, 0, None, FAKE, None, ws, None) == plmss.E_WORKSPACE
+    assert mi(FAKE, d, 0, None, FAKE, FAKE, ws - 1, None) == plmss.E_WORKSPACE
+    assert mi(FAKE, d, 1, None, FAKE, FAKE + 8, ws, None) == plmss.E_WORKSPACE
+    for dims in ((8, 8, 8), (2, 2, 2), (5, 7, 3), (9, 4, 1), (1, 4, 4), (4, 1, 4), (4, 4, 1), (7, 1, 1),
+                 (1, 1, 1), (512, 512, 512), (3, 1, 5)):
+        rows = lib.plmss_marching_rows(plmss.Dims(*dims))
+        assert rows == orc_rows(*dims), dims
+        assert rows == plmss.marching_rows(dims[::-1])
+        assert lib.plmss_marching_workspace_bytes(plmss.Dims(*dims)) >= 8 * ((rows + 255) // 256)
+    assert lib.plmss_marching_rows(plmss.Dims(0, 1, 1)) == -1
+    assert lib.plmss_marching_workspace_bytes(plmss.Dims(0, 1, 1)) == 0

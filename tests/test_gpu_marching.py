@@ -1,0 +1,184 @@
+"""GPU parity of the multi-label marching index (Sec. "Multi-Label Marching
+Triangles/Tetrahedra"): the HIP pass, called through the C ABI, against the
+CPU oracle on the same seeded label fields.  Codes and offsets are integers:
+every byte and every offset must be equal."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2303_15491_amd as plmss
+from paper_2303_15491_amd import fields
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    return _t
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _compare(torch, labels, mode, label=""):
+    _say(f"marching {label} shape={labels.shape} mode={mode}")
+    ref = oracle.marching(labels, mode)
+    codes, offs = plmss.marching_index(_dev(torch, labels), mode, with_codes=True)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(offs.cpu().numpy(), ref["row_offsets"], err_msg=f"{label} offsets")
+    np.testing.assert_array_equal(codes.cpu().numpy(), ref["codes"], err_msg=f"{label} codes")
+    # without codes the offsets are the same
+    none, offs2 = plmss.marching_index(_dev(torch, labels), mode, with_codes=False)
+    torch.cuda.synchronize()
+    assert none is None
+    np.testing.assert_array_equal(offs2.cpu().numpy(), ref["row_offsets"], err_msg=f"{label} offsets, no codes")
+    return ref
+
+
+# shapes (nz, ny, nx): ragged against the 64-cube lane chunks and the 16-row
+# wave / 64-row block split, one with more than 1024 count blocks (several
+# rounds of the block-sum scan), planar ones, and grids without cells
+SHAPES_3D = [(2, 2, 2), (3, 5, 130), (4, 3, 65), (9, 17, 64), (5, 9, 66), (12, 9, 70), (3, 300, 300),
+             (2, 2, 4097)]
+SHAPES_2D = [(2, 2), (5, 130), (300, 257), (5000, 5), (1025, 65)]
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 6])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_random_labels_3d(torch, k, mode):
+    for i, shape in enumerate(SHAPES_3D[:6]):
+        _compare(torch, fields.random_labels(shape, k, seed=100 * k + i), mode, f"k={k}")
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_random_labels_2d(torch, k, mode):
+    for i, shape in enumerate(SHAPES_2D):
+        _compare(torch, fields.random_labels(shape, k, seed=200 * k + i), mode, f"2d k={k}")
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_many_blocks(torch, mode):
+    _compare(torch, fields.random_labels(SHAPES_3D[6], 3, seed=7), mode, "3x300x300")
+    _compare(torch, fields.region_labels(SHAPES_3D[7], seed=8), mode, "2x2x4097")
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (7,), (3, 4, 1), (4, 1, 4), (4, 4, 1), (1, 1, 9), (2, 1, 1), (1, 6),
+                                   (6, 1), (1,)])
+def test_grids_without_cells(torch, shape):
+    labels = fields.random_labels(shape, 3, seed=1)
+    ref = _compare(torch, labels, 0, f"degenerate {shape}")
+    assert ref["rows"] == 0 and ref["total"] == 0
+
+
+def test_one_plane_is_planar(torch):
+    """A 3-D shape one plane thick is the 2-D grid of that plane."""
+    labels = fields.random_labels((6, 70), 3, seed=4)
+    r2 = _compare(torch, labels, 0, "plane")
+    r3 = _compare(torch, labels.reshape(1, 6, 70), 0, "plane as 3-D")
+    np.testing.assert_array_equal(r2["codes"], r3["codes"])
+    assert r3["cells_per_cube"] == 2
+
+
+def test_region_labels(torch):
+    for i, shape in enumerate([(40, 40, 40), (33, 65, 129), (1, 257, 255), (700, 700)]):
+        labels = fields.region_labels(shape, seed=30 + i)
+        for mode in (0, 1):
+            _compare(torch, labels, mode, f"regions {shape}")
+
+
+def test_every_tetrahedron_code_appears(torch):
+    """The random-label cases above reach all fifteen codes of the table."""
+    with open(os.path.join(GOLDEN, "tet_binary_codes.json")) as fh:
+        table = json.load(fh)
+    want = sorted(int(r["code"]) for r in table["rows"])
+    labels = fields.random_labels((6, 7, 70), 4, seed=3)
+    codes, _ = plmss.marching_index(_dev(torch, labels), 0, with_codes=True)
+    torch.cuda.synchronize()
+    assert sorted(set(codes.cpu().numpy().tolist())) == want
+
+
+def test_ms_labels_of_a_segmentation(torch):
+    """The index over the MS, ascending and descending labels of a real
+    segmentation, each side computing its own labels."""
+    f = fields.smoothed_noise((24, 40, 70), 1.5, seed=11)
+    ref = oracle.segment(f)
+    out = plmss.segment(_dev(torch, f))
+    torch.cuda.synchronize()
+    for key in ("ms", "asc", "desc"):
+        for mode in (0, 1):
+            r = oracle.marching(ref[key], mode)
+            codes, offs = plmss.marching_index(out[key], mode, with_codes=True)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(offs.cpu().numpy(), r["row_offsets"], err_msg=key)
+            np.testing.assert_array_equal(codes.cpu().numpy(), r["codes"], err_msg=key)
+
+
+def test_out_tensors_and_stream(torch):
+    labels = fields.random_labels((5, 9, 66), 3, seed=5)
+    ref = oracle.marching(labels, 0)
+    rows = plmss.marching_rows(labels.shape)
+    codes = torch.full((rows * 65 * 6 + 2,), 0xAB, dtype=torch.uint8, device="cuda")
+    offs = torch.full((rows + 1,), -1, dtype=torch.int64, device="cuda")
+    s = torch.cuda.Stream()
+    d = _dev(torch, labels)
+    torch.cuda.current_stream().synchronize()
+    with torch.cuda.stream(s):
+        c, o = plmss.marching_index(d, 0, out=(codes, offs), stream=s)
+    s.synchronize()
+    np.testing.assert_array_equal(o.cpu().numpy(), ref["row_offsets"])
+    np.testing.assert_array_equal(c.cpu().numpy(), ref["codes"])
+    assert codes[-2:].cpu().tolist() == [0xAB, 0xAB]  # nothing written past the cells
+
+
+def test_full_size_sampled_rows(torch):
+    """512^3 labels in the launch shape the measurement uses: every row's
+    count equals the count of its own 2 x 2 x nx slab under the oracle on
+    sampled rows (first, last, random), all codes are codes of the table, and
+    the counts that the codes imply add up to the offsets everywhere."""
+    with open(os.path.join(GOLDEN, "tet_binary_codes.json")) as fh:
+        table = json.load(fh)
+    n = 512
+    labels = fields.region_labels((n, n, n), seed=9)
+    rows = (n - 1) * (n - 1)
+    rng = np.random.Generator(np.random.PCG64(12))
+    sample = sorted(set([0, 1, n - 2, n - 1, rows - 1] + rng.integers(0, rows, size=48).tolist()))
+    d = _dev(torch, labels)
+    for mode in (0, 1):
+        _say(f"marching 512^3 mode={mode}")
+        codes, offs = plmss.marching_index(d, mode, with_codes=True)
+        torch.cuda.synchronize()
+        o = offs.cpu().numpy()
+        c = codes.cpu().numpy().reshape(rows, n - 1, 6)
+        assert o[0] == 0 and np.all(np.diff(o) >= 0)
+        for r in sample:
+            y, z = r % (n - 1), r // (n - 1)
+            slab = oracle.marching(labels[z:z + 2, y:y + 2, :], mode)
+            assert o[r + 1] - o[r] == slab["total"], r
+            np.testing.assert_array_equal(c[r].ravel(), slab["codes"], err_msg=f"row {r}")
+        # counts implied by the codes, with the table's own per-code figures
+        # (a boundary triangle: two labels, one vertex apart)
+        per_code = np.zeros(64, np.int8)
+        for row in table["rows"]:
+            lone = row["labels"] == 2 and row["separators"] == 1
+            per_code[int(row["code"])] = int(row["separators"]) if mode == 0 else int(lone)
+        valid = np.zeros(64, bool)
+        valid[[int(row["code"]) for row in table["rows"]]] = True
+        assert valid[c].all()
+        implied = per_code[c].sum(axis=(1, 2), dtype=np.int64)
+        np.testing.assert_array_equal(np.diff(o), implied)
