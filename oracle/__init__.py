@@ -63,6 +63,8 @@ def _load():
         lib.plmss_oracle_marching_rows.argtypes = [i64, i64, i64]
         lib.plmss_oracle_marching_rows.restype = ctypes.c_int64
         lib.plmss_oracle_marching.argtypes = [vp, i64, i64, i64, ctypes.c_int, vp, vp]
+        lib.plmss_oracle_marching_geometry.argtypes = [vp, i64, i64, i64, ctypes.c_int, vp, vp, i64]
+        lib.plmss_oracle_marching_geometry.restype = ctypes.c_int64
         for name in ("plmss_oracle_order", "plmss_oracle_steepest", "plmss_oracle_labels",
                      "plmss_oracle_ms", "plmss_oracle_segment", "plmss_oracle_trace",
                      "plmss_oracle_neighbours", "plmss_oracle_marching"):
@@ -221,3 +223,23 @@ def marching(labels: np.ndarray, mode: int = 0, with_codes: bool = True) -> dict
         raise OracleError(rc, "marching")
     return {"codes": codes if with_codes else None, "row_offsets": offsets, "total": int(offsets[-1]),
             "rows": rows, "cells_per_cube": per}
+
+
+def marching_geometry(labels: np.ndarray, mode: int = 0, capacity=None) -> dict:
+    """Multi-label marching geometry (Sec. "Multi-Label Marching
+    Triangles/Tetrahedra", case figures; "Triangulation Options") of an int32
+    label field: the primitives the index counts, in cell order.  Returns
+    ``xyz`` (float32, (T, 3, 3) triangles in 3-D, (T, 2, 2) segments in
+    2-D; grid units), ``sides`` (int32, (T, 2)) and ``count``."""
+    labels = np.ascontiguousarray(labels, dtype=np.int32)
+    nx, ny, nz = _dims(labels)
+    lib = _load()
+    if capacity is None:
+        capacity = marching(labels, mode, with_codes=False)["total"]
+    pts, dim = (3, 3) if nz > 1 else (2, 2)
+    xyz = np.zeros((max(capacity, 1), pts, dim), np.float32)
+    sides = np.zeros((max(capacity, 1), 2), np.int32)
+    n = int(lib.plmss_oracle_marching_geometry(_p(labels), nx, ny, nz, int(mode), _p(xyz), _p(sides), int(capacity)))
+    if n < 0:
+        raise OracleError(n, "marching_geometry")
+    return {"xyz": xyz[:n], "sides": sides[:n], "count": n}

@@ -468,3 +468,228 @@ int plmss_oracle_marching(const int32_t* labels, int64_t nx, int64_t ny, int64_t
     row_offsets[rows] = total;
     return ORC_OK;
 }
+
+/* ---- multi-label marching geometry (Sec. "Multi-Label Marching
+ * Triangles/Tetrahedra": the tetrahedron case figure, the triangle case
+ * figure, and "Triangulation Options") ---------------------------------------
+ *
+ * The primitives the index above counts, written out.  Same cells, same cell
+ * order (row, then x, then cell), and within a cell the order given below.
+ * Points are named by the set S of the cell's vertices they average: one
+ * vertex (a grid vertex), two (an edge midpoint), three (a face centre),
+ * four (the tetrahedron's centre).  A point's coordinates are exact
+ * multiples of 1/12 in grid units (vertex (x, y, z) sits at (x, y, z)); each
+ * coordinate is stored as the float nearest to that value (the numerator,
+ * an integer, divided by 12 in double precision, then rounded to float; the
+ * quotient is either exact or has a repeating binary expansion, so this
+ * single float rounding is the correctly rounded value).
+ *
+ * Cell vertices v0..v3 in path (= increasing id) order, labels L0..L3.
+ * Separators, tetrahedra, by how the labels split:
+ *   one label: none.
+ *   one vertex p apart, the others q < r < s:  (pq, pr, ps).
+ *   two and two, {v0, q} and {r, s} (r < s):  (v0r, v0s, qr), (v0s, qr, qs).
+ *   three labels, p < q equal, r < s single (face centres T1 = prs,
+ *   T2 = qrs):  (T1, T2, pr), (T2, pr, qr), (T1, T2, rs), (T1, T2, ps),
+ *   (T2, ps, qs).
+ *   four labels: for the faces 012, 013, 023, 123 in turn and each face's
+ *   edges ij, ik, jk in turn: (0123, face, edge).
+ * Every face of a tetrahedron is then cut as the triangle rule cuts it, so
+ * that neighbouring tetrahedra agree on their common face.
+ * Separators, triangles (2-D): two labels, p apart, q < r: (pq, pr); three
+ * labels: (012, 01), (012, 02), (012, 12).
+ * Boundaries: a tetrahedron with exactly three vertices of one label gives
+ * the triangle of those three (in vertex order); a triangle with exactly two
+ * labels gives the edge of its two equal vertices.
+ *
+ * sides[2] of a separator: the two labels it separates, the one whose first
+ * vertex comes first in the cell.  Of a boundary: the label of the equal
+ * vertices, then the other.
+ *
+ * xyz: 3-D float[T][3][3] (point, axis); 2-D float[T][2][2] (axis x, y).
+ * Either output may be NULL.  capacity: primitives that fit in the outputs;
+ * more is ORC_E_TOO_LARGE.  Returns the number of primitives, or a negative
+ * status.
+ */
+typedef struct {
+    float* xyz;
+    int32_t* sides;
+    int64_t n, cap;
+    int dim, pts;  /* dim 3 / 2; points per primitive 3 / 2 */
+    int64_t P[4][3];
+    const int32_t* L;
+} geo_out;
+
+/* Point = the average of the cell vertices in mask S (bit i = vertex i). */
+static void geo_point(const geo_out* o, int S, float* dst) {
+    int k = 0;
+    int64_t sum[3] = {0, 0, 0};
+    for (int i = 0; i < 4; ++i)
+        if (S >> i & 1) {
+            ++k;
+            for (int a = 0; a < 3; ++a) sum[a] += o->P[i][a];
+        }
+    for (int a = 0; a < o->dim; ++a) dst[a] = (float)((double)(sum[a] * (12 / k)) / 12.0);
+}
+
+static int geo_emit(geo_out* o, const int* S, int32_t side0, int32_t side1) {
+    if (o->n >= o->cap) return ORC_E_TOO_LARGE;
+    if (o->xyz)
+        for (int p = 0; p < o->pts; ++p) geo_point(o, S[p], o->xyz + (o->n * o->pts + p) * o->dim);
+    if (o->sides) {
+        o->sides[2 * o->n] = side0;
+        o->sides[2 * o->n + 1] = side1;
+    }
+    o->n += 1;
+    return ORC_OK;
+}
+
+#define BIT(i) (1 << (i))
+
+/* The two labels of vertices u and w, the one that first occurs first. */
+static void first_order(const int32_t* L, int nv, int u, int w, int32_t* s0, int32_t* s1) {
+    int fu = 0, fw = 0;
+    while (L[fu] != L[u]) ++fu;
+    while (L[fw] != L[w]) ++fw;
+    (void)nv;
+    *s0 = fu < fw ? L[u] : L[w];
+    *s1 = fu < fw ? L[w] : L[u];
+}
+
+static int geo_cell(geo_out* o, int nv, int mode) {
+    const int32_t* L = o->L;
+    int size[4] = {0, 0, 0, 0}, first[4], distinct = 0;
+    for (int i = 0; i < nv; ++i) {
+        int j = 0;
+        while (L[j] != L[i]) ++j;
+        first[i] = j;
+        size[j] += 1;
+        if (j == i) ++distinct;
+    }
+    int32_t s0, s1;
+    int rc = ORC_OK;
+    if (mode == 1) { /* boundaries */
+        if (distinct != 2) return ORC_OK;
+        int lone = -1;
+        for (int i = 0; i < nv; ++i)
+            if (size[first[i]] == 1) lone = i;
+        if (lone < 0) return ORC_OK; /* two and two */
+        int S[3], k = 0, kept = -1;
+        for (int i = 0; i < nv; ++i)
+            if (i != lone) {
+                S[k++] = BIT(i);
+                if (kept < 0) kept = i;
+            }
+        return geo_emit(o, S, L[kept], L[lone]);
+    }
+    if (distinct == 1) return ORC_OK;
+    if (nv == 3) { /* triangles */
+        if (distinct == 2) {
+            int p = 0;
+            for (int i = 0; i < 3; ++i)
+                if (size[first[i]] == 1) p = i;
+            int q = p == 0 ? 1 : 0, r = p == 2 ? 1 : 2;
+            int S[2] = {BIT(p) | BIT(q), BIT(p) | BIT(r)};
+            first_order(L, nv, p, q, &s0, &s1);
+            return geo_emit(o, S, s0, s1);
+        }
+        const int E[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+        for (int e = 0; e < 3 && rc == ORC_OK; ++e) {
+            int S[2] = {7, BIT(E[e][0]) | BIT(E[e][1])};
+            first_order(L, nv, E[e][0], E[e][1], &s0, &s1);
+            rc = geo_emit(o, S, s0, s1);
+        }
+        return rc;
+    }
+    if (distinct == 2) {
+        int lone = -1;
+        for (int i = 0; i < 4; ++i)
+            if (size[first[i]] == 1) lone = i;
+        if (lone >= 0) {
+            int S[3], k = 0, other = -1;
+            for (int i = 0; i < 4; ++i)
+                if (i != lone) {
+                    S[k++] = BIT(lone) | BIT(i);
+                    if (other < 0) other = i;
+                }
+            first_order(L, 4, lone, other, &s0, &s1);
+            return geo_emit(o, S, s0, s1);
+        }
+        /* two and two: q is v0's partner, r < s the other pair */
+        int q = -1, r = -1, s = -1;
+        for (int i = 1; i < 4; ++i) {
+            if (L[i] == L[0]) q = i;
+            else if (r < 0) r = i;
+            else s = i;
+        }
+        first_order(L, 4, 0, r, &s0, &s1);
+        int A[3] = {BIT(0) | BIT(r), BIT(0) | BIT(s), BIT(q) | BIT(r)};
+        int B[3] = {BIT(0) | BIT(s), BIT(q) | BIT(r), BIT(q) | BIT(s)};
+        rc = geo_emit(o, A, s0, s1);
+        return rc == ORC_OK ? geo_emit(o, B, s0, s1) : rc;
+    }
+    if (distinct == 3) {
+        int p = -1, q = -1, r = -1, s = -1;
+        for (int i = 0; i < 4; ++i) {
+            if (size[first[i]] == 2) {
+                if (p < 0) p = i;
+                else q = i;
+            } else if (r < 0) r = i;
+            else s = i;
+        }
+        const int T1 = BIT(p) | BIT(r) | BIT(s), T2 = BIT(q) | BIT(r) | BIT(s);
+        const int pr = BIT(p) | BIT(r), qr = BIT(q) | BIT(r), rs = BIT(r) | BIT(s);
+        const int ps = BIT(p) | BIT(s), qs = BIT(q) | BIT(s);
+        int tri[5][3] = {{T1, T2, pr}, {T2, pr, qr}, {T1, T2, rs}, {T1, T2, ps}, {T2, ps, qs}};
+        int sep[5][2] = {{p, r}, {p, r}, {r, s}, {p, s}, {p, s}};
+        for (int t = 0; t < 5 && rc == ORC_OK; ++t) {
+            first_order(L, 4, sep[t][0], sep[t][1], &s0, &s1);
+            rc = geo_emit(o, tri[t], s0, s1);
+        }
+        return rc;
+    }
+    /* four labels */
+    const int F[4][3] = {{0, 1, 2}, {0, 1, 3}, {0, 2, 3}, {1, 2, 3}};
+    for (int f = 0; f < 4 && rc == ORC_OK; ++f) {
+        const int face = BIT(F[f][0]) | BIT(F[f][1]) | BIT(F[f][2]);
+        const int E[3][2] = {{F[f][0], F[f][1]}, {F[f][0], F[f][2]}, {F[f][1], F[f][2]}};
+        for (int e = 0; e < 3 && rc == ORC_OK; ++e) {
+            int S[3] = {15, face, BIT(E[e][0]) | BIT(E[e][1])};
+            rc = geo_emit(o, S, L[E[e][0]], L[E[e][1]]);
+        }
+    }
+    return rc;
+}
+
+int64_t plmss_oracle_marching_geometry(const int32_t* labels, int64_t nx, int64_t ny, int64_t nz, int mode,
+                                       float* xyz, int32_t* sides, int64_t capacity) {
+    if (!labels || nx < 1 || ny < 1 || nz < 1 || (mode != 0 && mode != 1) || capacity < 0) return ORC_E_ARG;
+    const int64_t rows = plmss_oracle_marching_rows(nx, ny, nz);
+    const int three_d = nz > 1;
+    const int nv = three_d ? 4 : 3, ncells = three_d ? 6 : 2;
+    geo_out o;
+    o.xyz = xyz;
+    o.sides = sides;
+    o.n = 0;
+    o.cap = capacity;
+    o.dim = three_d ? 3 : 2;
+    o.pts = three_d ? 3 : 2;
+    for (int64_t r = 0; r < rows; ++r) {
+        const int64_t y = three_d ? r % (ny - 1) : r, z = three_d ? r / (ny - 1) : 0;
+        for (int64_t x = 0; x + 1 < nx; ++x) {
+            for (int t = 0; t < ncells; ++t) {
+                int32_t lab[4];
+                int64_t p[3] = {x, y, z};
+                for (int i = 0; i < nv; ++i) {
+                    if (i > 0) p[three_d ? PERM3[t][i - 1] : PERM2[t][i - 1]] += 1;
+                    for (int a = 0; a < 3; ++a) o.P[i][a] = p[a];
+                    lab[i] = labels[p[0] + nx * (p[1] + ny * p[2])];
+                }
+                o.L = lab;
+                const int rc = geo_cell(&o, nv, mode);
+                if (rc != ORC_OK) return rc;
+            }
+        }
+    }
+    return o.n;
+}

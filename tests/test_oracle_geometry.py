@@ -1,0 +1,242 @@
+"""Pins of the oracle's multi-label marching geometry (Sec. "Multi-Label
+Marching Triangles/Tetrahedra", the tetrahedron and triangle case figures,
+and "Triangulation Options"), checked against what the paper states of the
+result rather than against its own construction:
+
+* the number of primitives per cell is the one the index (and the paper's
+  table of codes) gives;
+* on every face of a tetrahedron the separating triangles cut the face
+  exactly as the triangle rule cuts a triangle of those labels, so
+  neighbouring tetrahedra agree and the surface has no holes; edges inside a
+  tetrahedron are shared by at least two triangles;
+* points are only where the case figures put them (midpoints of edges whose
+  ends differ, centres of faces with three labels, the centre of a
+  tetrahedron with four), each triangle separates the two labels it names;
+* a planar interface is tiled exactly (closed-form area / length);
+* coordinates are the correctly rounded floats of multiples of 1/12.
+"""
+import json
+import os
+from fractions import Fraction
+from itertools import combinations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2303_15491_amd import fields
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+PERM3 = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
+PERM2 = [(0, 1), (1, 0)]
+
+
+def _table():
+    with open(os.path.join(GOLDEN, "tet_binary_codes.json")) as fh:
+        return {int(r["code"]): r for r in json.load(fh)["rows"]}
+
+
+def _cells(labels):
+    """(cell vertices' grid coordinates, labels) in cell order."""
+    a = np.asarray(labels)
+    three = a.ndim == 3 and a.shape[0] > 1
+    if a.ndim == 2:
+        a = a[None]
+    nz, ny, nx = a.shape
+    out = []
+    rows = (ny - 1) * (nz - 1) if three else (ny - 1 if nz == 1 else 0)
+    for r in range(rows):
+        y, z = (r % (ny - 1), r // (ny - 1)) if three else (r, 0)
+        for x in range(nx - 1):
+            for perm in (PERM3 if three else PERM2):
+                p = [x, y, z]
+                verts = [tuple(p)]
+                for ax in perm:
+                    p[ax] += 1
+                    verts.append(tuple(p))
+                out.append((verts, [int(a[v[2], v[1], v[0]]) for v in verts]))
+    return out
+
+
+def _split(labels, mode, geo):
+    """Primitives of each cell, using the index's per-cell counts."""
+    idx = oracle.marching(labels, mode)
+    three = np.asarray(labels).ndim == 3 and np.asarray(labels).shape[0] > 1
+    table = _table()
+    per = []
+    for code in idx["codes"]:
+        if three:
+            row = table[int(code)]
+            per.append(row["separators"] if mode == 0 else int(row["labels"] == 2 and row["separators"] == 1))
+        else:
+            n_lab = 1 + (code >> 2 & 1) + (code & 3 == 2)
+            per.append({1: 0, 2: 1, 3: 3}[n_lab] if mode == 0 else int(n_lab == 2))
+    assert sum(per) == geo["count"] == idx["total"]
+    starts = np.concatenate([[0], np.cumsum(per)])
+    return [(starts[i], starts[i + 1]) for i in range(len(per))]
+
+
+def _key(pt):
+    k = np.rint(np.asarray(pt, np.float64) * 12).astype(np.int64)
+    assert np.allclose(k / 12.0, pt, atol=1e-4)
+    return tuple(int(v) for v in k)
+
+
+def _subset_of(verts, key):
+    """The set of cell vertices (local indices) whose average is the point."""
+    dim = len(key)
+    for k in range(1, len(verts) + 1):
+        for S in combinations(range(len(verts)), k):
+            tot = [sum(verts[i][a] for i in S) * (12 // k) for a in range(dim)]
+            if tuple(tot) == key:
+                return frozenset(S)
+    raise AssertionError(f"point {key} is no vertex, midpoint or centre of the cell")
+
+
+def _face_rule(lab, face):
+    """Separating segments of one triangle (local vertex indices) by the
+    triangle case figure: as frozensets of point subsets."""
+    i, j, k = face
+    L = {v: lab[v] for v in face}
+    distinct = len(set(L.values()))
+    if distinct == 1:
+        return set()
+    if distinct == 3:
+        c = frozenset(face)
+        return {frozenset({c, frozenset({a, b})}) for a, b in ((i, j), (i, k), (j, k))}
+    lone = [v for v in face if list(L.values()).count(L[v]) == 1][0]
+    q, r = [v for v in face if v != lone]
+    return {frozenset({frozenset({lone, q}), frozenset({lone, r})})}
+
+
+@pytest.mark.parametrize("k", [2, 3, 4, 5])
+@pytest.mark.parametrize("seed", [1, 2])
+def test_tetrahedra_faces_follow_the_triangle_rule(k, seed):
+    labels = fields.random_labels((4, 5, 6), k, seed=10 * k + seed)
+    geo = oracle.marching_geometry(labels, 0)
+    spans = _split(labels, 0, geo)
+    faces = list(combinations(range(4), 3))
+    for (verts, lab), (a, b) in zip(_cells(labels), spans):
+        edges = {}
+        for t in range(a, b):
+            pts = [_subset_of(verts, _key(p)) for p in geo["xyz"][t]]
+            assert len(set(pts)) == 3, "degenerate triangle"
+            for P in pts:  # only where the case figures put points
+                labs = {lab[v] for v in P}
+                if len(P) == 2:
+                    assert len(labs) == 2
+                elif len(P) == 3:
+                    assert len(labs) == 3
+                else:
+                    assert len(P) == 4 and len(set(lab)) == 4
+            A, B = (int(s) for s in geo["sides"][t])
+            assert A != B and A in lab and B in lab and lab.index(A) < lab.index(B)
+            for P in pts:
+                if len(P) == 2:
+                    assert {lab[v] for v in P} == {A, B}
+            for e in combinations(pts, 2):
+                key = frozenset(e)
+                edges[key] = edges.get(key, 0) + 1
+        for f in faces:
+            on_face = {e for e in edges if frozenset().union(*e) <= set(f)}
+            assert on_face == _face_rule(lab, f), (verts, lab, f)
+            assert all(edges[e] == 1 for e in on_face)
+        for e, n in edges.items():
+            if not any(frozenset().union(*e) <= set(f) for f in faces):
+                assert n >= 2, "open edge inside a tetrahedron"
+
+
+@pytest.mark.parametrize("k", [2, 3, 4])
+def test_triangles_follow_the_triangle_rule(k):
+    labels = fields.random_labels((7, 9), k, seed=k)
+    geo = oracle.marching_geometry(labels, 0)
+    for (verts, lab), (a, b) in zip(_cells(labels), _split(labels, 0, geo)):
+        segs = set()
+        for t in range(a, b):
+            pts = [_subset_of([v[:2] for v in verts], _key(p)) for p in geo["xyz"][t]]
+            segs.add(frozenset(pts))
+            A, B = (int(s) for s in geo["sides"][t])
+            assert A != B and lab.index(A) < lab.index(B)
+        assert segs == _face_rule(lab, (0, 1, 2)) and len(segs) == b - a
+
+
+@pytest.mark.parametrize("shape", [(4, 5, 6), (6, 7)])
+def test_boundaries_are_faces_of_three_equal_vertices(shape):
+    labels = fields.random_labels(shape, 2, seed=3)
+    geo = oracle.marching_geometry(labels, 1)
+    two = len(shape) == 2
+    for (verts, lab), (a, b) in zip(_cells(labels), _split(labels, 1, geo)):
+        for t in range(a, b):
+            pts = [_subset_of([v[:2] for v in verts] if two else verts, _key(p)) for p in geo["xyz"][t]]
+            assert all(len(P) == 1 for P in pts)
+            idx = sorted(next(iter(P)) for P in pts)
+            assert len({lab[i] for i in idx}) == 1
+            lone = [i for i in range(len(lab)) if i not in idx]
+            assert len(lone) == 1 and lab[lone[0]] != lab[idx[0]]
+            assert tuple(geo["sides"][t]) == (lab[idx[0]], lab[lone[0]])
+
+
+def _tri_area(t):
+    return 0.5 * np.linalg.norm(np.cross(t[1] - t[0], t[2] - t[0]))
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_planar_interface_is_tiled_exactly(axis):
+    """A step between two labels across one axis: the separators lie in the
+    mid plane and cover it exactly; the boundaries lie in the two planes of
+    vertices beside it and cover each exactly."""
+    n = (5, 6, 7)
+    nz, ny, nx = n
+    zz, yy, xx = np.meshgrid(range(nz), range(ny), range(nx), indexing="ij")
+    c = (xx, yy, zz)[axis]
+    cut = 2
+    labels = np.where(c >= cut, 7, 3).astype(np.int32)
+    ext = [nx, ny, nz]
+    area = np.prod([e - 1 for i, e in enumerate(ext) if i != axis])
+    sep = oracle.marching_geometry(labels, 0)
+    xyz = sep["xyz"].astype(np.float64)
+    assert np.all(xyz[:, :, axis] == cut - 0.5)
+    assert abs(sum(_tri_area(t) for t in xyz) - area) < 1e-9
+    assert set(map(tuple, sep["sides"].tolist())) == {(3, 7)}
+    bnd = oracle.marching_geometry(labels, 1)
+    b = bnd["xyz"].astype(np.float64)
+    for plane in (cut - 1, cut):
+        on = np.all(b[:, :, axis] == plane, axis=1)
+        assert abs(sum(_tri_area(t) for t in b[on]) - area) < 1e-9
+    assert np.all(np.isin(b[:, :, axis], [cut - 1, cut]))
+
+
+def test_planar_interface_2d():
+    labels = np.where(np.arange(9)[None, :] >= 4, 1, 0).repeat(6, 0).astype(np.int32)
+    sep = oracle.marching_geometry(labels, 0)
+    s = sep["xyz"].astype(np.float64)
+    assert np.all(s[:, :, 0] == 3.5)
+    assert abs(np.abs(s[:, 1, 1] - s[:, 0, 1]).sum() - 5) < 1e-12
+    bnd = oracle.marching_geometry(labels, 1)
+    b = bnd["xyz"].astype(np.float64)
+    for line in (3.0, 4.0):
+        on = np.all(b[:, :, 0] == line, axis=1)
+        assert abs(np.abs(b[on, 1, 1] - b[on, 0, 1]).sum() - 5) < 1e-12
+
+
+def test_coordinates_are_correctly_rounded_twelfths():
+    labels = fields.random_labels((3, 4, 40), 4, seed=9)
+    xyz = oracle.marching_geometry(labels, 0)["xyz"].ravel()
+    seen = 0
+    for c in np.unique(xyz):
+        m = int(np.rint(float(c) * 12))
+        exact = Fraction(m, 12)
+        f = np.float32(c)
+        lo, hi = np.nextafter(f, np.float32(-np.inf)), np.nextafter(f, np.float32(np.inf))
+        d = abs(Fraction(float(f)) - exact)
+        assert d <= abs(Fraction(float(lo)) - exact) and d <= abs(Fraction(float(hi)) - exact)
+        seen += Fraction(float(f)) != exact
+    assert seen > 0  # thirds and sixths are not exact floats
+
+
+def test_empty_and_capacity():
+    assert oracle.marching_geometry(np.zeros((3, 3, 3), np.int32), 0)["count"] == 0
+    assert oracle.marching_geometry(np.arange(5, dtype=np.int32), 0)["count"] == 0
+    labels = fields.random_labels((3, 3, 3), 3, seed=1)
+    with pytest.raises(oracle.OracleError):
+        oracle.marching_geometry(labels, 0, capacity=1)
