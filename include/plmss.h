@@ -191,6 +191,43 @@ int plmss_marching_index(const int32_t* labels, plmss_dims dims, int32_t mode, u
                          uint64_t* row_offsets, void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * Multi-label marching geometry (paper, same section: the tetrahedron and
+ * triangle case figures, and "Triangulation Options"): the primitives that
+ * plmss_marching_index counts, written at its offsets.  row_offsets is that
+ * call's output for the same labels, dims and mode (device, rows + 1
+ * entries); primitive j of row r is written at index row_offsets[r] + j.
+ *
+ * Primitives, per cell in cell order.  Points are named by the set of cell
+ * vertices they average (a vertex, an edge midpoint, a face centre, the
+ * tetrahedron's centre); cell vertices v0..v3 in path order.
+ *   Separators, tetrahedra: one vertex p apart, others q < r < s:
+ *   (pq, pr, ps); two and two {v0, q}, {r, s}: (v0r, v0s, qr),
+ *   (v0s, qr, qs); three labels, p < q equal, r < s single, T1 = prs,
+ *   T2 = qrs: (T1, T2, pr), (T2, pr, qr), (T1, T2, rs), (T1, T2, ps),
+ *   (T2, ps, qs); four labels: for faces 012, 013, 023, 123 and each face's
+ *   edges in order, (v0v1v2v3, face, edge).  Triangles (2-D): p apart,
+ *   q < r: (pq, pr); three labels: (012, 01), (012, 02), (012, 12).
+ *   Every tetrahedron face is thus cut as the triangle rule cuts a triangle,
+ *   so that neighbouring tetrahedra agree.
+ *   Boundaries: the triangle of the three equal vertices of a tetrahedron
+ *   with one vertex apart; the edge of the two equal vertices of a triangle
+ *   with two labels.
+ *
+ * xyz (device float, nullable, 4-byte aligned): 3-D float[capacity][3][3]
+ * (point, axis x y z), 2-D float[capacity][2][2], in grid units (vertex
+ * (x, y, z) at (x, y, z)).  Coordinates are multiples of 1/12; each is the
+ * float nearest to its exact value.  sides (device int32, nullable, 8-byte
+ * aligned): int32[capacity][2], the two labels a separator separates, in the
+ * order of their first vertex in the cell; for a boundary, the label of the
+ * equal vertices, then the other.  Primitives at indices >= capacity are not
+ * written (capacity = row_offsets[rows] writes all).  No workspace.
+ * Returns PLMSS_OK, PLMSS_E_ARG (NULL labels/row_offsets, bad mode,
+ * misaligned outputs), PLMSS_E_DIMS, PLMSS_E_TOO_LARGE or PLMSS_E_HIP.
+ */
+int plmss_marching_geometry(const int32_t* labels, plmss_dims dims, int32_t mode, const uint64_t* row_offsets,
+                            uint64_t capacity, float* xyz, int32_t* sides, void* stream);
+
+/*
  * Many fields of different sizes in one pass: the same results as calling
  * plmss_segment on each job, computed by one launch per step over all fields
  * together.  jobs is a HOST array of n_jobs entries; the sum of their N must
@@ -264,7 +301,8 @@ int plmss_plan_launch_graph(plmss_plan* plan, void* workspace, size_t workspace_
 #define PLMSS_KERNEL_ORDER_LAST 14   /* order field: last pass (sorted ids, or (id, position) by range) */
 #define PLMSS_KERNEL_ORDER_REGROUP 15 /* order field: (id, position) regrouped by id chunk */
 #define PLMSS_KERNEL_MARCH 16      /* marching index: cell codes and row counts */
-#define PLMSS_KERNEL_KINDS 17
+#define PLMSS_KERNEL_MARCH_GEOMETRY 17 /* marching geometry: primitives written out */
+#define PLMSS_KERNEL_KINDS 18
 
 typedef struct plmss_trace plmss_trace;
 plmss_trace* plmss_trace_create(int32_t max_launches);

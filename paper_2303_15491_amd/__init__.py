@@ -15,7 +15,7 @@ import os
 
 __all__ = ["PlmssError", "library", "segment", "order_field", "steepest", "compress", "ms_ids",
            "segment_batch", "workspace_bytes", "batch_workspace_bytes", "batch_needs", "Plan",
-           "tune_get", "tune_set", "KNOBS", "marching_rows", "marching_index", "MARCH_SEPARATORS",
+           "tune_get", "tune_set", "KNOBS", "marching_rows", "marching_index", "marching_geometry", "MARCH_SEPARATORS",
            "MARCH_BOUNDARIES"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -63,6 +63,8 @@ _SIGNATURES = {
     "plmss_marching_workspace_bytes": ([Dims], ctypes.c_size_t),
     "plmss_marching_index": ([ctypes.c_void_p, Dims, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                               ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
+    "plmss_marching_geometry": ([ctypes.c_void_p, Dims, ctypes.c_int32, ctypes.c_void_p, ctypes.c_uint64,
+                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "plmss_batch_workspace_bytes": ([ctypes.c_int32, ctypes.POINTER(Job)], ctypes.c_size_t),
     "plmss_segment_batch": ([ctypes.c_int32, ctypes.POINTER(Job), ctypes.c_void_p, ctypes.c_size_t,
                              ctypes.c_void_p], ctypes.c_int),
@@ -325,6 +327,39 @@ def marching_index(labels, mode: int = MARCH_SEPARATORS, with_codes: bool = Fals
     _check(lib.plmss_marching_index(_ptr(labels), dims, int(mode), _ptr(codes), _ptr(offs), _ptr(ws), ws.numel(),
                                     _stream(stream)), "plmss_marching_index")
     return (codes[:cells] if codes is not None else None), offs
+
+
+def marching_geometry(labels, mode: int = MARCH_SEPARATORS, with_xyz: bool = True, with_sides: bool = True,
+                      row_offsets=None, stream=None, out=None):
+    """Multi-label marching geometry of an int32 device label field.
+
+    Returns ``(xyz, sides, count)``: ``xyz`` a float32 device tensor of shape
+    (count, 3, 3) triangles in 3-D or (count, 2, 2) segments in 2-D (grid
+    units), ``sides`` an int32 (count, 2) tensor of the labels each primitive
+    separates (either None when not asked for).  ``row_offsets`` is
+    :func:`marching_index`'s output for the same labels and mode; without it
+    the index runs first.  Reading the total synchronises with the device
+    unless ``out=(xyz, sides, count)`` supplies the outputs and their
+    capacity.
+    """
+    torch = _torch()
+    if not labels.is_cuda or not labels.is_contiguous() or labels.dtype != torch.int32:
+        raise ValueError("labels must be a contiguous int32 device tensor")
+    dims = dims_of(labels.shape)
+    three = dims.nz > 1
+    pts = (3, 3) if three else (2, 2)
+    if row_offsets is None:
+        _, row_offsets = marching_index(labels, mode, with_codes=False, stream=stream)
+    if out is not None:
+        xyz, sides, count = out
+        count = int(count)
+    else:
+        count = int(row_offsets[-1].item())
+        xyz = torch.empty((max(count, 1),) + pts, dtype=torch.float32, device=labels.device) if with_xyz else None
+        sides = torch.empty((max(count, 1), 2), dtype=torch.int32, device=labels.device) if with_sides else None
+    _check(library().plmss_marching_geometry(_ptr(labels), dims, int(mode), _ptr(row_offsets), count, _ptr(xyz),
+                                             _ptr(sides), _stream(stream)), "plmss_marching_geometry")
+    return (xyz[:count] if xyz is not None else None), (sides[:count] if sides is not None else None), count
 
 
 def _jobs(fields, outs):

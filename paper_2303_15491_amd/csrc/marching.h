@@ -261,3 +261,279 @@ __global__ __launch_bounds__(kBlock) void k_march_offsets(uint64_t* row_offsets,
 }
 
 }  // namespace plmss
+
+namespace plmss {
+
+// ---- geometry pass -----------------------------------------------------------------------
+// The primitives of every cell, written at the offsets of the index pass.  A
+// primitive is encoded in 16 bits: three (in 2-D two) point masks of 4 bits
+// (bit i = cell vertex i; the point is the average of those vertices) and
+// two 2-bit vertex indices u < w whose labels are the two it separates (for
+// a boundary: a vertex of the equal ones, then the odd one).
+struct GeoLut {
+    uint8_t base[32], count[32];
+    uint16_t prim[64];
+};
+
+constexpr uint16_t geo_prim(int s0, int s1, int s2, int u, int w) {
+    return uint16_t(s0 | (s1 << 4) | (s2 << 8) | (u << 12) | (w << 14));
+}
+
+// Primitives of one cell from its local labels (k[i] = first vertex with
+// vertex i's label): tetrahedra (nv = 4) or triangles (nv = 3).
+constexpr int geo_cell(const int* k, int nv, int mode, uint16_t* out) {
+    int n = 0, groups = 0, size[4] = {0, 0, 0, 0};
+    for (int i = 0; i < nv; ++i) {
+        size[k[i]] += 1;
+        groups += k[i] == i;
+    }
+    int lone = -1;
+    for (int i = 0; i < nv; ++i)
+        if (size[k[i]] == 1 && groups == 2) lone = i;
+    auto bit = [](int i) { return 1 << i; };
+    if (mode == 1) {  // boundaries: the equal vertices of a cell with one vertex apart
+        if (lone < 0) return 0;
+        int v[3] = {0, 0, 0}, m = 0;
+        for (int i = 0; i < nv; ++i)
+            if (i != lone) v[m++] = i;
+        out[n++] = geo_prim(bit(v[0]), bit(v[1]), nv == 4 ? bit(v[2]) : 0, v[0], lone);
+        return n;
+    }
+    if (groups == 1) return 0;
+    if (nv == 3) {
+        if (groups == 2) {  // the edge between the two edges that leave the odd vertex
+            int o[2] = {0, 0}, m = 0;
+            for (int i = 0; i < 3; ++i)
+                if (i != lone) o[m++] = i;
+            out[n++] = geo_prim(bit(lone) | bit(o[0]), bit(lone) | bit(o[1]), 0, k[lone] < k[o[0]] ? k[lone] : k[o[0]],
+                                k[lone] < k[o[0]] ? k[o[0]] : k[lone]);
+            return n;
+        }
+        for (int a = 0; a < 3; ++a)  // three labels: centre to each edge midpoint
+            for (int b = a + 1; b < 3; ++b) out[n++] = geo_prim(7, bit(a) | bit(b), 0, a, b);
+        return n;
+    }
+    if (groups == 2 && lone >= 0) {
+        int o[3] = {0, 0, 0}, m = 0;
+        for (int i = 0; i < 4; ++i)
+            if (i != lone) o[m++] = i;
+        const int g0 = k[lone], g1 = k[o[0]];
+        out[n++] = geo_prim(bit(lone) | bit(o[0]), bit(lone) | bit(o[1]), bit(lone) | bit(o[2]), g0 < g1 ? g0 : g1,
+                            g0 < g1 ? g1 : g0);
+        return n;
+    }
+    if (groups == 2) {  // two and two: vertex 0 with q, r < s apart
+        int q = 0, r = -1, s = 0;
+        for (int i = 1; i < 4; ++i) {
+            if (k[i] == 0) q = i;
+            else if (r < 0) r = i;
+            else s = i;
+        }
+        out[n++] = geo_prim(bit(0) | bit(r), bit(0) | bit(s), bit(q) | bit(r), 0, r);
+        out[n++] = geo_prim(bit(0) | bit(s), bit(q) | bit(r), bit(q) | bit(s), 0, r);
+        return n;
+    }
+    if (groups == 3) {  // p < q share a label, r < s alone
+        int p = -1, q = 0, r = -1, s = 0;
+        for (int i = 0; i < 4; ++i) {
+            if (size[k[i]] == 2) {
+                if (p < 0) p = i;
+                else q = i;
+            } else if (r < 0) r = i;
+            else s = i;
+        }
+        const int t1 = bit(p) | bit(r) | bit(s), t2 = bit(q) | bit(r) | bit(s);
+        auto lo = [](int a, int b) { return a < b ? a : b; };
+        auto hi = [](int a, int b) { return a < b ? b : a; };
+        out[n++] = geo_prim(t1, t2, bit(p) | bit(r), lo(p, r), hi(p, r));
+        out[n++] = geo_prim(t2, bit(p) | bit(r), bit(q) | bit(r), lo(p, r), hi(p, r));
+        out[n++] = geo_prim(t1, t2, bit(r) | bit(s), r, s);
+        out[n++] = geo_prim(t1, t2, bit(p) | bit(s), lo(p, s), hi(p, s));
+        out[n++] = geo_prim(t2, bit(p) | bit(s), bit(q) | bit(s), lo(p, s), hi(p, s));
+        return n;
+    }
+    // four labels: the centre, each face's centre and each of its edges
+    const int faces[4][3] = {{0, 1, 2}, {0, 1, 3}, {0, 2, 3}, {1, 2, 3}};
+    for (int f = 0; f < 4; ++f) {
+        const int a = faces[f][0], b = faces[f][1], c = faces[f][2];
+        const int fm = bit(a) | bit(b) | bit(c);
+        out[n++] = geo_prim(15, fm, bit(a) | bit(b), a, b);
+        out[n++] = geo_prim(15, fm, bit(a) | bit(c), a, c);
+        out[n++] = geo_prim(15, fm, bit(b) | bit(c), b, c);
+    }
+    return n;
+}
+
+// Tables over all codes (invalid codes get no primitives).
+constexpr GeoLut make_geo_lut(bool three_d, int mode) {
+    GeoLut t{};
+    int n = 0;
+    const int nv = three_d ? 4 : 3;
+    for (int code = 0; code < 32; ++code) {
+        int k[4] = {0, 0, 0, 0};
+        if (three_d) k[1] = code >> 4, k[2] = (code >> 2) & 3, k[3] = code & 3;
+        else k[1] = (code >> 2) & 1, k[2] = code & 3;
+        bool valid = three_d || code < 8;
+        for (int i = 0; i < nv; ++i) valid = valid && k[i] <= i && k[k[i]] == k[i];
+        t.base[code] = uint8_t(n);
+        const int m = valid ? geo_cell(k, nv, mode, t.prim + n) : 0;
+        t.count[code] = uint8_t(m);
+        n += m;
+    }
+    return t;
+}
+
+__constant__ const GeoLut kGeoLut[4] = {make_geo_lut(false, 0), make_geo_lut(false, 1), make_geo_lut(true, 0),
+                                        make_geo_lut(true, 1)};
+
+constexpr int kGeoWaves = kWavesPerBlock;
+
+// One wave per row of cubes; its lanes take 64 cubes at a time, count their
+// primitives, scan the counts over the wave, keep each cube's corner labels
+// and offset in LDS, and then write the chunk's primitives with consecutive
+// lanes on consecutive primitives (each lane finds its cube by a binary
+// search over the offsets, then its cell and its entry of the table).
+template <bool THREE_D, int MODE>
+__global__ __launch_bounds__(kBlock) void k_march_geometry(const int32_t* labels, int nx, int ny, uint32_t rows,
+                                                           const uint64_t* row_offsets, uint64_t capacity,
+                                                           float* xyz, int32_t* sides) {
+    constexpr int kCells = THREE_D ? 6 : 2;
+    constexpr int kCorners = THREE_D ? 8 : 4;
+    constexpr int kPts = THREE_D ? 3 : 2;
+    constexpr int kDim = THREE_D ? 3 : 2;
+    __shared__ int32_t s_lab[kGeoWaves][kCorners][kWave];
+    __shared__ uint32_t s_off[kGeoWaves][kWave + 1];
+    __shared__ uint32_t s_cnt[kGeoWaves][kWave];  // 4 bits per cell
+    const GeoLut& lut = kGeoLut[(THREE_D ? 2 : 0) + MODE];
+    const int lane = lane_id();
+    const int w = __builtin_amdgcn_readfirstlane(wave_id());
+    const uint32_t r = xcd_block(blockIdx.x, gridDim.x) * kGeoWaves + uint32_t(w);
+    if (r >= rows) return;  // no block-wide barrier below
+    const int ncube = nx - 1;
+    const uint32_t y = THREE_D ? r % uint32_t(ny - 1) : r, z = THREE_D ? r / uint32_t(ny - 1) : 0u;
+    const size_t plane = size_t(nx) * size_t(ny);
+    const int32_t* p00 = labels + (size_t(z) * size_t(ny) + y) * size_t(nx);
+    uint64_t base = gmem(row_offsets)[r];
+    // the tetrahedra's second and third path vertices (corner bit 0 = +x,
+    // 1 = +y, 2 = +z) and their axis order
+    constexpr int v1[6] = {1, 1, 2, 2, 4, 4}, v2[6] = {3, 5, 3, 6, 5, 6};
+    for (int x0 = 0; x0 < ncube; x0 += kWave) {
+        const int x = x0 + lane;
+        const bool valid = x < ncube;
+        const int xc = valid ? x : ncube - 1;
+        int32_t l[8];
+        l[0] = gmem(p00)[xc];
+        l[1] = gmem(p00)[xc + 1];
+        l[2] = gmem(p00 + nx)[xc];
+        l[3] = gmem(p00 + nx)[xc + 1];
+        if (THREE_D) {
+            l[4] = gmem(p00 + plane)[xc];
+            l[5] = gmem(p00 + plane)[xc + 1];
+            l[6] = gmem(p00 + plane + nx)[xc];
+            l[7] = gmem(p00 + plane + nx)[xc + 1];
+        }
+        uint32_t packed = 0, total = 0;
+#pragma unroll
+        for (int t = 0; t < kCells; ++t) {
+            uint32_t code;
+            if constexpr (THREE_D) {
+                const int32_t a = l[0], b = l[v1[t]], c = l[v2[t]], d = l[7];
+                code = (b == a ? 0u : 16u) | ((c == a ? 0u : c == b ? 1u : 2u) << 2) |
+                       (d == a ? 0u : d == b ? 1u : d == c ? 2u : 3u);
+            } else {
+                const int32_t a = l[0], b = l[t == 0 ? 1 : 2], c = l[3];
+                code = (b == a ? 0u : 4u) | (c == a ? 0u : c == b ? 1u : 2u);
+            }
+            const uint32_t m = valid ? uint32_t(lut.count[code]) : 0u;
+            packed |= m << (4 * t);
+            total += m;
+        }
+        // exclusive scan of the cube totals over the wave
+        uint32_t inc = total;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t v = uint32_t(__shfl_up(int(inc), d, kWave));
+            if (lane >= d) inc += v;
+        }
+        const uint32_t chunk = uint32_t(__shfl(int(inc), kWave - 1, kWave));
+#pragma unroll
+        for (int i = 0; i < kCorners; ++i) s_lab[w][i][lane] = l[i];
+        s_off[w][lane] = inc - total;
+        s_cnt[w][lane] = packed;
+        if (lane == 0) s_off[w][kWave] = chunk;
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (uint32_t j0 = 0; j0 < chunk; j0 += kWave) {
+            const uint32_t i = j0 + uint32_t(lane);
+            if (i < chunk) {
+                int c = 0;
+#pragma unroll
+                for (int step = kWave / 2; step > 0; step >>= 1)
+                    if (s_off[w][c + step] <= i) c += step;
+                uint32_t rem = i - s_off[w][c];
+                const uint32_t pk = s_cnt[w][c];
+                int t = 0;  // the cell: skip the cells before it
+#pragma unroll
+                for (int q = 0; q < kCells - 1; ++q) {
+                    const uint32_t m = (pk >> (4 * q)) & 15u;
+                    const bool past = t == q && rem >= m;
+                    rem -= past ? m : 0u;
+                    t += past ? 1 : 0;
+                }
+                // the cell's vertices (corner indices) and their labels
+                int cv[4];
+                if constexpr (THREE_D) {
+                    cv[0] = 0, cv[3] = 7;
+                    cv[1] = t == 0 || t == 1 ? 1 : t == 2 || t == 3 ? 2 : 4;
+                    cv[2] = t == 0 || t == 2 ? 3 : t == 1 || t == 4 ? 5 : 6;
+                } else {
+                    cv[0] = 0, cv[1] = t == 0 ? 1 : 2, cv[2] = 3, cv[3] = 3;
+                }
+                int32_t lab[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) lab[v] = s_lab[w][cv[v]][c];
+                uint32_t code;
+                if constexpr (THREE_D)
+                    code = (lab[1] == lab[0] ? 0u : 16u) |
+                           ((lab[2] == lab[0] ? 0u : lab[2] == lab[1] ? 1u : 2u) << 2) |
+                           (lab[3] == lab[0] ? 0u : lab[3] == lab[1] ? 1u : lab[3] == lab[2] ? 2u : 3u);
+                else
+                    code = (lab[1] == lab[0] ? 0u : 4u) | (lab[2] == lab[0] ? 0u : lab[2] == lab[1] ? 1u : 2u);
+                const uint32_t e = lut.prim[lut.base[code] + rem];
+                const uint64_t out = base + i;
+                if (out < capacity) {
+                    if (xyz) {
+                        // corner offsets of the cell's vertices: vertex v has
+                        // +1 along an axis once the path has stepped along it
+                        const int ox = x0 + c, oy = int(y), oz = int(z);
+                        float* dst = xyz + out * (kPts * kDim);
+#pragma unroll
+                        for (int p = 0; p < kPts; ++p) {
+                            const uint32_t S = (e >> (4 * p)) & 15u;
+                            const int k = __builtin_popcount(S);
+                            const int scale = 12 / k;
+                            int sx = 0, sy = 0, sz = 0;
+#pragma unroll
+                            for (int v = 0; v < (THREE_D ? 4 : 3); ++v)
+                                if (S >> v & 1) sx += cv[v] & 1, sy += (cv[v] >> 1) & 1, sz += (cv[v] >> 2) & 1;
+                            const double inv12 = 1.0 / 12.0;
+                            gmem(dst)[p * kDim + 0] = float(double(12 * int64_t(ox) + scale * sx) * inv12);
+                            gmem(dst)[p * kDim + 1] = float(double(12 * int64_t(oy) + scale * sy) * inv12);
+                            if (THREE_D) gmem(dst)[p * kDim + 2] = float(double(12 * int64_t(oz) + scale * sz) * inv12);
+                        }
+                    }
+                    if (sides) {
+                        const int u = (e >> 12) & 3, v = (e >> 14) & 3;
+                        typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
+                        gmem(reinterpret_cast<i32x2*>(sides))[out] = i32x2{lab[u], lab[v]};
+                    }
+                }
+            }
+        }
+        base += chunk;
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+}  // namespace plmss

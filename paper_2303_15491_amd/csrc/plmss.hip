@@ -989,6 +989,34 @@ int plmss_marching_index(const int32_t* labels, plmss_dims dims, int32_t mode, u
     return launch_status();
 }
 
+int plmss_marching_geometry(const int32_t* labels, plmss_dims dims, int32_t mode, const uint64_t* row_offsets,
+                            uint64_t capacity, float* xyz, int32_t* sides, void* stream) {
+    if (!labels || !row_offsets || (mode != PLMSS_MARCH_SEPARATORS && mode != PLMSS_MARCH_BOUNDARIES))
+        return PLMSS_E_ARG;
+    if ((xyz && (reinterpret_cast<uintptr_t>(xyz) & 3u)) || (sides && (reinterpret_cast<uintptr_t>(sides) & 7u)))
+        return PLMSS_E_ARG;
+    uint64_t n;
+    const int rc = check_dims(dims, &n);
+    if (rc != PLMSS_OK) return rc;
+    const uint64_t rows = uint64_t(march_rows(dims));
+    if (rows == 0 || (!xyz && !sides)) return PLMSS_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const unsigned blocks = unsigned((rows + kGeoWaves - 1) / kGeoWaves);
+    const int nx = int(dims.nx), ny = int(dims.ny);
+    launch(PLMSS_KERNEL_MARCH_GEOMETRY, s, [&] {
+        auto go = [&](auto kernel) {
+            kernel<<<blocks, kBlock, 0, s>>>(labels, nx, ny, uint32_t(rows), row_offsets, capacity, xyz, sides);
+        };
+        switch ((dims.nz > 1 ? 2 : 0) | (mode ? 1 : 0)) {
+            case 0: go(k_march_geometry<false, 0>); break;
+            case 1: go(k_march_geometry<false, 1>); break;
+            case 2: go(k_march_geometry<true, 0>); break;
+            default: go(k_march_geometry<true, 1>); break;
+        }
+    });
+    return launch_status();
+}
+
 size_t plmss_batch_workspace_bytes(int32_t n_jobs, const plmss_job* jobs) {
     BatchLayout B;
     if (batch_layout(n_jobs, jobs, scan_depth(), &B) != PLMSS_OK) return 0;
@@ -1222,7 +1250,7 @@ const char* plmss_kernel_name(int32_t kind) {
     static const char* names[PLMSS_KERNEL_KINDS] = {
         "misc", "radix_hist", "radix_digit_scan", "radix_scatter", "steepest", "jump", "prefix_sum",
         "pair_compact", "pair_rank", "ms_final", "order_hist", "order_scatter", "order_invert",
-        "order_first", "order_last", "order_regroup", "march_count"};
+        "order_first", "order_last", "order_regroup", "march_count", "march_geometry"};
     return (kind >= 0 && kind < PLMSS_KERNEL_KINDS) ? names[kind] : "unknown";
 }
 

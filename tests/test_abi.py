@@ -153,3 +153,19 @@ def test_marching_argument_errors_and_rows():
         assert lib.plmss_marching_workspace_bytes(plmss.Dims(*dims)) >= 8 * ((rows + 255) // 256)
     assert lib.plmss_marching_rows(plmss.Dims(0, 1, 1)) == -1
     assert lib.plmss_marching_workspace_bytes(plmss.Dims(0, 1, 1)) == 0
+
+
+def test_marching_geometry_argument_errors():
+    lib = plmss.library()
+    d = plmss.Dims(8, 8, 8)
+    g = lib.plmss_marching_geometry
+    assert g(None, d, 0, FAKE, 10, FAKE, FAKE, None) == plmss.E_ARG
+    assert g(FAKE, d, 0, None, 10, FAKE, FAKE, None) == plmss.E_ARG
+    assert g(FAKE, d, 3, FAKE, 10, FAKE, FAKE, None) == plmss.E_ARG
+    assert g(FAKE, d, 0, FAKE, 10, FAKE + 2, FAKE, None) == plmss.E_ARG  # xyz not 4-byte aligned
+    assert g(FAKE, d, 0, FAKE, 10, FAKE, FAKE + 4, None) == plmss.E_ARG  # sides not 8-byte aligned
+    assert g(FAKE, plmss.Dims(0, 8, 8), 0, FAKE, 10, FAKE, FAKE, None) == plmss.E_DIMS
+    assert g(FAKE, plmss.Dims(2048, 2048, 512), 0, FAKE, 10, FAKE, FAKE, None) == plmss.E_TOO_LARGE
+    # grids without cells and calls without outputs launch nothing
+    assert g(FAKE, plmss.Dims(8, 1, 1), 0, FAKE, 10, FAKE, FAKE, None) == plmss.OK
+    assert g(FAKE, d, 1, FAKE, 10, None, None, None) == plmss.OK

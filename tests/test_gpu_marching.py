@@ -182,3 +182,111 @@ def test_full_size_sampled_rows(torch):
         assert valid[c].all()
         implied = per_code[c].sum(axis=(1, 2), dtype=np.int64)
         np.testing.assert_array_equal(np.diff(o), implied)
+
+
+# ---- geometry pass ------------------------------------------------------------------------
+
+def _bits(a):
+    return np.ascontiguousarray(a).view(np.int32)
+
+
+def _compare_geo(torch, labels, mode, label=""):
+    _say(f"geometry {label} shape={labels.shape} mode={mode}")
+    ref = oracle.marching_geometry(labels, mode)
+    xyz, sides, count = plmss.marching_geometry(_dev(torch, labels), mode)
+    torch.cuda.synchronize()
+    assert count == ref["count"], label
+    np.testing.assert_array_equal(_bits(xyz.cpu().numpy()), _bits(ref["xyz"]), err_msg=f"{label} xyz")
+    np.testing.assert_array_equal(sides.cpu().numpy(), ref["sides"], err_msg=f"{label} sides")
+    return ref
+
+
+@pytest.mark.parametrize("k", [2, 3, 4, 6])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_geometry_random_labels(torch, k, mode):
+    for i, shape in enumerate(SHAPES_3D[:6] + SHAPES_2D[:4]):
+        _compare_geo(torch, fields.random_labels(shape, k, seed=300 * k + i), mode, f"k={k}")
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_geometry_region_and_segmentation_labels(torch, mode):
+    for i, shape in enumerate([(40, 40, 40), (33, 65, 129), (1, 257, 255), (300, 301)]):
+        _compare_geo(torch, fields.region_labels(shape, seed=50 + i), mode, f"regions {shape}")
+    f = fields.smoothed_noise((24, 40, 70), 1.5, seed=11)
+    ref = oracle.segment(f)
+    out = plmss.segment(_dev(torch, f))
+    torch.cuda.synchronize()
+    for key in ("ms", "asc", "desc"):
+        r = oracle.marching_geometry(ref[key], mode)
+        xyz, sides, count = plmss.marching_geometry(out[key], mode)
+        torch.cuda.synchronize()
+        assert count == r["count"]
+        np.testing.assert_array_equal(_bits(xyz.cpu().numpy()), _bits(r["xyz"]), err_msg=key)
+        np.testing.assert_array_equal(sides.cpu().numpy(), r["sides"], err_msg=key)
+
+
+def test_geometry_capacity_and_partial_outputs(torch):
+    labels = fields.random_labels((5, 9, 66), 4, seed=6)
+    ref = oracle.marching_geometry(labels, 0)
+    n = ref["count"]
+    d = _dev(torch, labels)
+    _, offs = plmss.marching_index(d, 0)
+    cap = n // 3
+    xyz = torch.full((n, 3, 3), -7.0, dtype=torch.float32, device="cuda")
+    sides = torch.full((n, 2), -7, dtype=torch.int32, device="cuda")
+    plmss.marching_geometry(d, 0, row_offsets=offs, out=(xyz, sides, cap))
+    torch.cuda.synchronize()
+    x, s = xyz.cpu().numpy(), sides.cpu().numpy()
+    np.testing.assert_array_equal(_bits(x[:cap]), _bits(ref["xyz"][:cap]))
+    np.testing.assert_array_equal(s[:cap], ref["sides"][:cap])
+    assert np.all(x[cap:] == -7.0) and np.all(s[cap:] == -7)
+    only_xyz, none, _ = plmss.marching_geometry(d, 0, with_sides=False)
+    none2, only_sides, _ = plmss.marching_geometry(d, 0, with_xyz=False)
+    torch.cuda.synchronize()
+    assert none is None and none2 is None
+    np.testing.assert_array_equal(_bits(only_xyz.cpu().numpy()), _bits(ref["xyz"]))
+    np.testing.assert_array_equal(only_sides.cpu().numpy(), ref["sides"])
+
+
+def test_geometry_grids_without_cells(torch):
+    for shape in [(1, 1, 1), (7,), (3, 4, 1), (4, 1, 4), (1, 6)]:
+        labels = fields.random_labels(shape, 3, seed=2)
+        xyz, sides, count = plmss.marching_geometry(_dev(torch, labels), 0)
+        torch.cuda.synchronize()
+        assert count == 0 and xyz.numel() == 0 and sides.numel() == 0
+
+
+def _twelfths(a):
+    k = np.rint(a.astype(np.float64) * 12).astype(np.int64)
+    # every value is the float nearest to its twelfth
+    np.testing.assert_array_equal(_bits(a), _bits((k / 12.0).astype(np.float32)))
+    return k
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_geometry_full_size_sampled_rows(torch, mode):
+    """512^3 region labels in the launch shape the measurement uses: the
+    primitives of sampled rows equal the oracle's on the row's own
+    2 x 2 x nx slab (shifted by the row's y, z; compared in exact twelfths,
+    with every float checked to be the nearest to its twelfth)."""
+    n = 512
+    labels = fields.region_labels((n, n, n), seed=9)
+    rows = (n - 1) * (n - 1)
+    rng = np.random.Generator(np.random.PCG64(13))
+    sample = sorted(set([0, n - 2, rows - 1] + rng.integers(0, rows, size=24).tolist()))
+    d = _dev(torch, labels)
+    _say(f"geometry 512^3 mode={mode}")
+    _, offs = plmss.marching_index(d, mode)
+    xyz, sides, count = plmss.marching_geometry(d, mode, row_offsets=offs)
+    torch.cuda.synchronize()
+    o = offs.cpu().numpy()
+    assert count == o[-1]
+    for r in sample:
+        y, z = r % (n - 1), r // (n - 1)
+        slab = oracle.marching_geometry(labels[z:z + 2, y:y + 2, :], mode)
+        a, b = int(o[r]), int(o[r + 1])
+        assert b - a == slab["count"], r
+        got = xyz[a:b].cpu().numpy()
+        want = _twelfths(slab["xyz"]) + 12 * np.array([0, y, z], np.int64)
+        np.testing.assert_array_equal(_twelfths(got), want, err_msg=f"row {r}")
+        np.testing.assert_array_equal(sides[a:b].cpu().numpy(), slab["sides"], err_msg=f"row {r}")
