@@ -383,8 +383,50 @@ constexpr GeoLut make_geo_lut(bool three_d, int mode) {
     return t;
 }
 
-__constant__ const GeoLut kGeoLut[4] = {make_geo_lut(false, 0), make_geo_lut(false, 1), make_geo_lut(true, 0),
-                                        make_geo_lut(true, 1)};
+// The same tables expanded per cell shape (tetrahedron t of a cube, or
+// triangle t of a square): each primitive's points as offsets from the cube's
+// low corner in twelfths of a grid step, 4 bits per axis (point p, axis a at
+// bit 12p + 4a; a point averaging |S| vertices is (12 / |S|) times the sum
+// of their corner offsets), and the two vertices u, w at bits 36 and 38.
+struct GeoTab {
+    uint8_t base[32], count[32];
+    uint64_t ent[6][64];
+};
+
+constexpr GeoTab make_geo_tab(bool three_d, int mode) {
+    const GeoLut l = make_geo_lut(three_d, mode);
+    GeoTab t{};
+    for (int c = 0; c < 32; ++c) t.base[c] = l.base[c], t.count[c] = l.count[c];
+    const int cells = three_d ? 6 : 2, npts = three_d ? 3 : 2, dims = three_d ? 3 : 2;
+    // corners (bit 0 = +x, 1 = +y, 2 = +z) of each cell's path vertices
+    const int tet[6][4] = {{0, 1, 3, 7}, {0, 1, 5, 7}, {0, 2, 3, 7}, {0, 2, 6, 7}, {0, 4, 5, 7}, {0, 4, 6, 7}};
+    const int tri[2][4] = {{0, 1, 3, 0}, {0, 2, 3, 0}};
+    for (int cell = 0; cell < cells; ++cell) {
+        const int* cv = three_d ? tet[cell] : tri[cell];
+        for (int e = 0; e < 64; ++e) {
+            const uint32_t prim = l.prim[e];
+            uint64_t E = 0;
+            for (int p = 0; p < npts; ++p) {
+                const int S = int(prim >> (4 * p)) & 15;
+                int k = 0;
+                for (int i = 0; i < 4; ++i) k += (S >> i) & 1;
+                if (k == 0) continue;
+                for (int a = 0; a < dims; ++a) {
+                    int d = 0;
+                    for (int i = 0; i < 4; ++i)
+                        if ((S >> i) & 1) d += (cv[i] >> a) & 1;
+                    E |= uint64_t((12 / k) * d) << (12 * p + 4 * a);
+                }
+            }
+            E |= uint64_t((prim >> 12) & 3) << 36 | uint64_t((prim >> 14) & 3) << 38;
+            t.ent[cell][e] = E;
+        }
+    }
+    return t;
+}
+
+__constant__ const GeoTab kGeoTab[4] = {make_geo_tab(false, 0), make_geo_tab(false, 1), make_geo_tab(true, 0),
+                                        make_geo_tab(true, 1)};
 
 constexpr int kGeoWaves = kWavesPerBlock;
 
@@ -404,7 +446,16 @@ __global__ __launch_bounds__(kBlock) void k_march_geometry(const int32_t* labels
     __shared__ int32_t s_lab[kGeoWaves][kCorners][kWave];
     __shared__ uint32_t s_off[kGeoWaves][kWave + 1];
     __shared__ uint32_t s_cnt[kGeoWaves][kWave];  // 4 bits per cell
-    const GeoLut& lut = kGeoLut[(THREE_D ? 2 : 0) + MODE];
+    constexpr int kVals = kPts * kDim;              // floats per primitive
+    __shared__ float s_xyz[kGeoWaves][kWave * kVals];
+    __shared__ GeoTab s_tab;
+    {
+        static_assert(sizeof(GeoTab) % 4 == 0, "copied in words");
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(&kGeoTab[(THREE_D ? 2 : 0) + MODE]);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(&s_tab);
+        for (int i = threadIdx.x; i < int(sizeof(GeoTab) / 4); i += kBlock) dst[i] = src[i];
+        __syncthreads();
+    }
     const int lane = lane_id();
     const int w = __builtin_amdgcn_readfirstlane(wave_id());
     const uint32_t r = xcd_block(blockIdx.x, gridDim.x) * kGeoWaves + uint32_t(w);
@@ -444,7 +495,7 @@ __global__ __launch_bounds__(kBlock) void k_march_geometry(const int32_t* labels
                 const int32_t a = l[0], b = l[t == 0 ? 1 : 2], c = l[3];
                 code = (b == a ? 0u : 4u) | (c == a ? 0u : c == b ? 1u : 2u);
             }
-            const uint32_t m = valid ? uint32_t(lut.count[code]) : 0u;
+            const uint32_t m = valid ? uint32_t(s_tab.count[code]) : 0u;
             packed |= m << (4 * t);
             total += m;
         }
@@ -500,35 +551,41 @@ __global__ __launch_bounds__(kBlock) void k_march_geometry(const int32_t* labels
                            (lab[3] == lab[0] ? 0u : lab[3] == lab[1] ? 1u : lab[3] == lab[2] ? 2u : 3u);
                 else
                     code = (lab[1] == lab[0] ? 0u : 4u) | (lab[2] == lab[0] ? 0u : lab[2] == lab[1] ? 1u : 2u);
-                const uint32_t e = lut.prim[lut.base[code] + rem];
-                const uint64_t out = base + i;
-                if (out < capacity) {
-                    if (xyz) {
-                        // corner offsets of the cell's vertices: vertex v has
-                        // +1 along an axis once the path has stepped along it
-                        const int ox = x0 + c, oy = int(y), oz = int(z);
-                        float* dst = xyz + out * (kPts * kDim);
+                const uint64_t e = s_tab.ent[t][s_tab.base[code] + rem];
+                if (xyz) {
+                    // a point: (12 * corner + its offset in twelfths) / 12,
+                    // staged in LDS so that the wave's stores are contiguous
+                    const int64_t o12[3] = {12 * int64_t(x0 + c), 12 * int64_t(y), 12 * int64_t(z)};
+                    const double inv12 = 1.0 / 12.0;
 #pragma unroll
-                        for (int p = 0; p < kPts; ++p) {
-                            const uint32_t S = (e >> (4 * p)) & 15u;
-                            const int k = __builtin_popcount(S);
-                            const int scale = 12 / k;
-                            int sx = 0, sy = 0, sz = 0;
+                    for (int p = 0; p < kPts; ++p)
 #pragma unroll
-                            for (int v = 0; v < (THREE_D ? 4 : 3); ++v)
-                                if (S >> v & 1) sx += cv[v] & 1, sy += (cv[v] >> 1) & 1, sz += (cv[v] >> 2) & 1;
-                            const double inv12 = 1.0 / 12.0;
-                            gmem(dst)[p * kDim + 0] = float(double(12 * int64_t(ox) + scale * sx) * inv12);
-                            gmem(dst)[p * kDim + 1] = float(double(12 * int64_t(oy) + scale * sy) * inv12);
-                            if (THREE_D) gmem(dst)[p * kDim + 2] = float(double(12 * int64_t(oz) + scale * sz) * inv12);
-                        }
-                    }
-                    if (sides) {
-                        const int u = (e >> 12) & 3, v = (e >> 14) & 3;
-                        typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
-                        gmem(reinterpret_cast<i32x2*>(sides))[out] = i32x2{lab[u], lab[v]};
-                    }
+                        for (int a = 0; a < kDim; ++a)
+                            s_xyz[w][lane * kVals + p * kDim + a] =
+                                float(double(o12[a] + int64_t((e >> (12 * p + 4 * a)) & 15u)) * inv12);
                 }
+                const uint64_t out = base + i;
+                if (sides && out < capacity) {
+                    const int u = int(e >> 36) & 3, v = int(e >> 38) & 3;
+                    typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
+                    gmem(reinterpret_cast<i32x2*>(sides))[out] = i32x2{lab[u], lab[v]};
+                }
+            }
+            if (xyz) {  // the staged points: consecutive lanes on consecutive floats
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                const uint64_t first = base + j0;
+                const uint32_t nvals = min(uint32_t(kWave), chunk - j0) * uint32_t(kVals);
+                const uint64_t room = capacity > first ? (capacity - first) * kVals : 0;
+                const uint32_t lim = room < nvals ? uint32_t(room) : nvals;
+                float* dst = xyz + first * kVals;
+#pragma unroll
+                for (int q = 0; q < kVals; ++q) {
+                    const uint32_t idx = uint32_t(q * kWave + lane);
+                    if (idx < lim) gmem(dst)[idx] = s_xyz[w][idx];
+                }
+                __builtin_amdgcn_wave_barrier();
             }
         }
         base += chunk;
