@@ -290,3 +290,15 @@ def test_geometry_full_size_sampled_rows(torch, mode):
         want = _twelfths(slab["xyz"]) + 12 * np.array([0, y, z], np.int64)
         np.testing.assert_array_equal(_twelfths(got), want, err_msg=f"row {r}")
         np.testing.assert_array_equal(sides[a:b].cpu().numpy(), slab["sides"], err_msg=f"row {r}")
+
+
+def test_extreme_label_values(torch):
+    """Labels are compared for equality only: any int32 values, the extremes
+    and negatives included, give the codes and primitives of their pattern."""
+    vals = np.array([np.iinfo(np.int32).min, -1, 0, np.iinfo(np.int32).max], np.int32)
+    for shape in [(4, 6, 70), (9, 65)]:
+        labels = vals[fields.random_labels(shape, 4, seed=21)]
+        for mode in (0, 1):
+            _compare(torch, labels, mode, f"extremes {shape}")
+            ref = _compare_geo(torch, labels, mode, f"extremes {shape}")
+            assert set(np.unique(ref["sides"])) <= set(vals.tolist())
