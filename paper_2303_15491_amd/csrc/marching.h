@@ -464,6 +464,7 @@ __global__ __launch_bounds__(kBlock) void k_march_geometry(const int32_t* labels
     const uint32_t y = THREE_D ? r % uint32_t(ny - 1) : r, z = THREE_D ? r / uint32_t(ny - 1) : 0u;
     const size_t plane = size_t(nx) * size_t(ny);
     const int32_t* p00 = labels + (size_t(z) * size_t(ny) + y) * size_t(nx);
+    const bool narrow = nx < (1 << 27) && ny < (1 << 27) && y < (1u << 27) && z < (1u << 27);
     uint64_t base = gmem(row_offsets)[r];
     // the tetrahedra's second and third path vertices (corner bit 0 = +x,
     // 1 = +y, 2 = +z) and their axis order
@@ -555,14 +556,29 @@ __global__ __launch_bounds__(kBlock) void k_march_geometry(const int32_t* labels
                 if (xyz) {
                     // a point: (12 * corner + its offset in twelfths) / 12,
                     // staged in LDS so that the wave's stores are contiguous
-                    const int64_t o12[3] = {12 * int64_t(x0 + c), 12 * int64_t(y), 12 * int64_t(z)};
                     const double inv12 = 1.0 / 12.0;
+                    const uint32_t elo = uint32_t(e), ehi = uint32_t(e >> 32);
+                    auto twelfths = [&](int p, int a) {  // the 4-bit offset of point p, axis a
+                        const int bit = 12 * p + 4 * a;
+                        return int((bit < 32 ? elo >> bit : ehi >> (bit - 32)) & 15u);
+                    };
+                    if (narrow) {  // 12 * coordinate fits int32
+                        const int o12[3] = {12 * (x0 + c), 12 * int(y), 12 * int(z)};
 #pragma unroll
-                    for (int p = 0; p < kPts; ++p)
+                        for (int p = 0; p < kPts; ++p)
 #pragma unroll
-                        for (int a = 0; a < kDim; ++a)
-                            s_xyz[w][lane * kVals + p * kDim + a] =
-                                float(double(o12[a] + int64_t((e >> (12 * p + 4 * a)) & 15u)) * inv12);
+                            for (int a = 0; a < kDim; ++a)
+                                s_xyz[w][lane * kVals + p * kDim + a] =
+                                    float(double(o12[a] + twelfths(p, a)) * inv12);
+                    } else {
+                        const int64_t o12[3] = {12 * int64_t(x0 + c), 12 * int64_t(y), 12 * int64_t(z)};
+#pragma unroll
+                        for (int p = 0; p < kPts; ++p)
+#pragma unroll
+                            for (int a = 0; a < kDim; ++a)
+                                s_xyz[w][lane * kVals + p * kDim + a] =
+                                    float(double(o12[a] + twelfths(p, a)) * inv12);
+                    }
                 }
                 const uint64_t out = base + i;
                 if (sides && out < capacity) {

@@ -302,3 +302,20 @@ def test_extreme_label_values(torch):
             _compare(torch, labels, mode, f"extremes {shape}")
             ref = _compare_geo(torch, labels, mode, f"extremes {shape}")
             assert set(np.unique(ref["sides"])) <= set(vals.tolist())
+
+
+def test_geometry_long_rows_use_wide_coordinates(torch):
+    """Rows longer than 2^27 vertices: twelfths of a coordinate no longer fit
+    int32, the kernel takes its 64-bit path; labels vary only near the far end
+    (a long 2-D strip, 2^27 + 200 vertices wide)."""
+    nx = (1 << 27) + 200
+    labels = np.zeros((2, nx), np.int32)
+    labels[:, -150:] = fields.random_labels((2, 150), 3, seed=4)
+    for mode in (0, 1):
+        ref = oracle.marching_geometry(labels, mode)
+        xyz, sides, count = plmss.marching_geometry(_dev(torch, labels), mode)
+        torch.cuda.synchronize()
+        assert count == ref["count"] > 0
+        np.testing.assert_array_equal(_bits(xyz.cpu().numpy()), _bits(ref["xyz"]))
+        np.testing.assert_array_equal(sides.cpu().numpy(), ref["sides"])
+        assert ref["xyz"][:, :, 0].min() > (1 << 27) - 200
