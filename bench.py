@@ -29,7 +29,9 @@ HBM_PEAK_GBS = 8000.0
 # array the kernel is defined on is read once and written once (float32 field,
 # int32 labels, 32-bit keys).
 #   steepest      : read order or f (4), write up, dn (8)
-#   jump          : read up, dn (8), write asc, desc (8)
+#   jump          : read up, dn (8), write asc, desc (8) and each vertex's
+#                   MS pair record index into ms (4); the listed pair records
+#                   (12 B per listed pair, about 7% of N) are left out
 #   ms_final      : read slot (4), write ms (4)
 #   order_first   : read f (4), write key and id (8)
 #   order_scatter : read key and id (8), write key and id (8)  (a middle pass)
@@ -40,7 +42,7 @@ HBM_PEAK_GBS = 8000.0
 #                   [0]; read sorted ids (4), write order (4 / w) [w >= 2]
 #   order_regroup : read (id, position) (8), write it regrouped by id chunk (8)
 #   order_hist    : read key (4)
-ALGO_BYTES = {"steepest": 12.0, "jump": 16.0, "ms_final": 8.0, "order_first": 12.0, "order_scatter": 16.0,
+ALGO_BYTES = {"steepest": 12.0, "jump": 20.0, "ms_final": 8.0, "order_first": 12.0, "order_scatter": 16.0,
               "order_hist": 4.0, "order_regroup": 16.0}
 
 
