@@ -596,10 +596,15 @@ __global__ __launch_bounds__(kBlock) void k_march_geometry(const int32_t* labels
                 const uint64_t room = capacity > first ? (capacity - first) * kVals : 0;
                 const uint32_t lim = room < nvals ? uint32_t(room) : nvals;
                 float* dst = xyz + first * kVals;
+                if (lim == uint32_t(kWave * kVals)) {  // a full set: no per-store bound
 #pragma unroll
-                for (int q = 0; q < kVals; ++q) {
-                    const uint32_t idx = uint32_t(q * kWave + lane);
-                    if (idx < lim) gmem(dst)[idx] = s_xyz[w][idx];
+                    for (int q = 0; q < kVals; ++q) gmem(dst)[q * kWave + lane] = s_xyz[w][q * kWave + lane];
+                } else {
+#pragma unroll
+                    for (int q = 0; q < kVals; ++q) {
+                        const uint32_t idx = uint32_t(q * kWave + lane);
+                        if (idx < lim) gmem(dst)[idx] = s_xyz[w][idx];
+                    }
                 }
                 __builtin_amdgcn_wave_barrier();
             }
