@@ -323,6 +323,17 @@ def bench_marching(torch, plmss, lib, labels, steps: int, warmup: int, cpu_plane
         res["cpu_baseline"] = {"value": sl.size / (t1 - t0) / 1e6, "unit": "Mvertices/s", "cores": 1,
                                "kind": "oracle", "sample": f"serial C oracle with codes on {tuple(sl.shape)}, "
                                                            f"{t1 - t0:.2f} s"}
+        # the geometry oracle on a thinner slab (its output is ~44 B per primitive in host memory)
+        gl = np.ascontiguousarray(labels[:min(cpu_planes, 8)].cpu().numpy())
+        cap = oracle.marching(gl, 0, with_codes=False)["total"]
+        t0 = time.perf_counter()
+        g = oracle.marching_geometry(gl, 0, capacity=cap)
+        t1 = time.perf_counter()
+        res["geometry_cpu_baseline"] = {"value": g["count"] / (t1 - t0) / 1e6, "unit": "M primitives/s", "cores": 1,
+                                        "kind": "oracle",
+                                        "sample": f"serial C oracle, separators with points and sides, on "
+                                                  f"{tuple(gl.shape)} ({g['count']} triangles), {t1 - t0:.2f} s"}
+        del g
     del codes, offs, ws
     return res
 
