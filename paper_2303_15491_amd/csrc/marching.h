@@ -1,7 +1,8 @@
-// Multi-label marching index (Sec. "Multi-Label Marching Triangles/Tetrahedra"):
-// the label code of every cell and the number of separating primitives per
-// row of cells, then the rows' exclusive prefix, so that a geometry pass can
-// write every row's primitives at a known offset.
+// Multi-label marching triangles/tetrahedra (Sec. "Multi-Label Marching
+// Triangles/Tetrahedra"), in two passes as the paper splits them.  The index:
+// the label code of every cell and the number of separating (or boundary)
+// primitives per row of cells, then the rows' exclusive prefix.  The
+// geometry: every row's primitives written at its offset.
 //
 // Cells: in 3-D the six Kuhn tetrahedra of every cube (the cut along the cube
 // diagonal (1,1,1), the same triangulation as the neighbour scan), in 2-D
@@ -74,9 +75,9 @@ __device__ __forceinline__ uint64_t block_exclusive_u64(uint64_t x, uint64_t* tm
 // Counts.  Each wave owns kMarchRowsPerWave consecutive rows; its lanes take
 // 64 consecutive cubes along x and walk the wave's rows in order, so that the
 // lower y face of a cube (corners 0, 1, 4, 5; bit 0 = +x, bit 1 = +y, bit 2 =
-// +z) and the label equalities on it come from the upper face of the cube
-// below in the previous row; only the first row of the wave and of each z
-// slab reads it fresh.  A cell's count depends only on E (above): a
+// +z) and the label equalities on it come from the upper face of the same
+// cube of the previous row (y - 1); only the first row of the wave and of each
+// z slab reads it fresh.  A cell's count depends only on E (above): a
 // tetrahedron (0, v1, v2, 7) has E = [0=v1] + [0=v2] + [0=7] + [v1=v2] +
 // [v1=7] + [v2=7], and of these the six [0=k], [k=7] serve two tetrahedra
 // each and [0=7] all six.  Every lane keeps its own running count per row in
