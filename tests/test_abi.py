@@ -95,6 +95,10 @@ def test_python_binding_refuses_host_tensors():
     torch = pytest.importorskip("torch")
     with pytest.raises(ValueError):
         plmss.segment(torch.zeros(4, 4))
+    with pytest.raises(ValueError):
+        plmss.marching_index(torch.zeros(4, 4, dtype=torch.int32))
+    with pytest.raises(ValueError):
+        plmss.marching_geometry(torch.zeros(4, 4, dtype=torch.int32))
 
 
 def test_tuning_knobs_validate_ranges():
