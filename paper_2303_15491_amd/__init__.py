@@ -15,7 +15,7 @@ import os
 
 __all__ = ["PlmssError", "library", "segment", "order_field", "steepest", "compress", "ms_ids",
            "segment_batch", "workspace_bytes", "batch_workspace_bytes", "batch_needs", "Plan",
-           "tune_get", "tune_set", "KNOBS", "marching_rows", "marching_index", "marching_geometry", "MARCH_SEPARATORS",
+           "tune_get", "tune_set", "KNOBS", "marching_rows", "marching_index", "marching_geometry", "marching_geometry_union", "MARCH_SEPARATORS",
            "MARCH_BOUNDARIES"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -360,6 +360,28 @@ def marching_geometry(labels, mode: int = MARCH_SEPARATORS, with_xyz: bool = Tru
     _check(library().plmss_marching_geometry(_ptr(labels), dims, int(mode), _ptr(row_offsets), count, _ptr(xyz),
                                              _ptr(sides), _stream(stream)), "plmss_marching_geometry")
     return (xyz[:count] if xyz is not None else None), (sides[:count] if sides is not None else None), count
+
+
+def marching_geometry_union(asc, desc, mode: int = MARCH_SEPARATORS, stream=None):
+    """Geometry of the union of the ascending and descending segmentations
+    (Sec. "Triangulation Options"): the primitives of ``asc`` followed by
+    those of ``desc``, where the two surfaces meet they intersect.  Returns
+    ``(xyz, sides, count_asc, count_desc)``; each half is one
+    :func:`marching_geometry` call written into its part of one output."""
+    torch = _torch()
+    offs = [marching_index(t, mode, stream=stream)[1] for t in (asc, desc)]
+    counts = [int(o[-1].item()) for o in offs]
+    dims = dims_of(asc.shape)
+    pts = (3, 3) if dims.nz > 1 else (2, 2)
+    total = counts[0] + counts[1]
+    xyz = torch.empty((max(total, 1),) + pts, dtype=torch.float32, device=asc.device)
+    sides = torch.empty((max(total, 1), 2), dtype=torch.int32, device=asc.device)
+    start = 0
+    for t, o, c in zip((asc, desc), offs, counts):
+        if c:
+            marching_geometry(t, mode, row_offsets=o, stream=stream, out=(xyz[start:start + c], sides[start:start + c], c))
+        start += c
+    return xyz[:total], sides[:total], counts[0], counts[1]
 
 
 def _jobs(fields, outs):

@@ -319,3 +319,17 @@ def test_geometry_long_rows_use_wide_coordinates(torch):
         np.testing.assert_array_equal(_bits(xyz.cpu().numpy()), _bits(ref["xyz"]))
         np.testing.assert_array_equal(sides.cpu().numpy(), ref["sides"])
         assert ref["xyz"][:, :, 0].min() > (1 << 27) - 200
+
+
+def test_geometry_union_of_ascending_and_descending(torch):
+    f = fields.smoothed_noise((16, 30, 50), 1.5, seed=12)
+    ref = oracle.segment(f)
+    out = plmss.segment(_dev(torch, f))
+    torch.cuda.synchronize()
+    for mode in (0, 1):
+        xyz, sides, ca, cd = plmss.marching_geometry_union(out["asc"], out["desc"], mode)
+        torch.cuda.synchronize()
+        ra, rd = oracle.marching_geometry(ref["asc"], mode), oracle.marching_geometry(ref["desc"], mode)
+        assert (ca, cd) == (ra["count"], rd["count"])
+        np.testing.assert_array_equal(_bits(xyz.cpu().numpy()), _bits(np.concatenate([ra["xyz"], rd["xyz"]])))
+        np.testing.assert_array_equal(sides.cpu().numpy(), np.concatenate([ra["sides"], rd["sides"]]))
