@@ -13,6 +13,8 @@ result rather than against its own construction:
   ends differ, centres of faces with three labels, the centre of a
   tetrahedron with four), each triangle separates the two labels it names;
 * a planar interface is tiled exactly (closed-form area / length);
+* a vertex with a label of its own is enclosed by a closed surface (a sphere:
+  Euler characteristic 2) through the midpoints of its edges, or by its link;
 * coordinates are the correctly rounded floats of multiples of 1/12.
 """
 import json
@@ -240,3 +242,54 @@ def test_empty_and_capacity():
     labels = fields.random_labels((3, 3, 3), 3, seed=1)
     with pytest.raises(oracle.OracleError):
         oracle.marching_geometry(labels, 0, capacity=1)
+
+
+def _closed_surface(tris):
+    """(points, edges, faces, every edge shared by exactly two faces)."""
+    keys = [tuple(_key(p) for p in t) for t in tris]
+    points = {p for t in keys for p in t}
+    edges = {}
+    for t in keys:
+        for a, b in combinations(t, 2):
+            e = frozenset((a, b))
+            edges[e] = edges.get(e, 0) + 1
+    return points, edges, len(keys), all(n == 2 for n in edges.values())
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_isolated_vertex_is_enclosed_by_a_sphere(mode):
+    """One vertex with a label of its own inside a constant field: it lies in
+    24 tetrahedra of the Kuhn cut and has 14 neighbours.  The separators are
+    the 24 corner triangles through the midpoints of its 14 edges, the
+    boundaries the 24 faces opposite it (its link); either way a closed
+    surface of Euler characteristic 2."""
+    labels = np.zeros((5, 5, 5), np.int32)
+    labels[2, 2, 2] = 9
+    geo = oracle.marching_geometry(labels, mode)
+    assert geo["count"] == 24
+    points, edges, faces, closed = _closed_surface(geo["xyz"].astype(np.float64))
+    assert closed and len(points) - len(edges) + faces == 2
+    centre = np.array([2, 2, 2], np.float64) * 12
+    off = {tuple(int(v) for v in (np.array(p) - centre)) for p in points}
+    dirs = {(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 0), (1, 0, 1), (0, 1, 1), (1, 1, 1)}
+    dirs |= {tuple(-v for v in d) for d in dirs}
+    scale = 6 if mode == 0 else 12  # edge midpoints, or the neighbours themselves
+    assert off == {tuple(scale * v for v in d) for d in dirs}
+    assert set(map(tuple, geo["sides"].tolist())) == ({(0, 9), (9, 0)} if mode == 0 else {(0, 9)})
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_isolated_vertex_2d_is_enclosed_by_a_hexagon(mode):
+    labels = np.zeros((5, 5), np.int32)
+    labels[2, 2] = 4
+    geo = oracle.marching_geometry(labels, mode)
+    assert geo["count"] == 6
+    segs = [tuple(_key(p) for p in s) for s in geo["xyz"].astype(np.float64)]
+    deg = {}
+    for s in segs:
+        for p in s:
+            deg[p] = deg.get(p, 0) + 1
+    assert len(deg) == 6 and all(d == 2 for d in deg.values())  # one closed loop of six edges
+    scale = 6 if mode == 0 else 12
+    dirs = {(1, 0), (0, 1), (1, 1), (-1, 0), (0, -1), (-1, -1)}
+    assert {(p[0] - 24, p[1] - 24) for p in deg} == {(scale * a, scale * b) for a, b in dirs}
