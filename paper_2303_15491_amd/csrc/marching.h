@@ -388,7 +388,8 @@ constexpr GeoLut make_geo_lut(bool three_d, int mode) {
 // triangle t of a square): each primitive's points as offsets from the cube's
 // low corner in twelfths of a grid step, 4 bits per axis (point p, axis a at
 // bit 12p + 4a; a point averaging |S| vertices is (12 / |S|) times the sum
-// of their corner offsets), and the two vertices u, w at bits 36 and 38.
+// of their corner offsets), the two vertices u, w at bits 36 and 38, and
+// their corners (3 bits each) at bits 40 and 43.
 struct GeoTab {
     uint8_t base[32], count[32];
     uint64_t ent[6][64];
@@ -419,7 +420,8 @@ constexpr GeoTab make_geo_tab(bool three_d, int mode) {
                     E |= uint64_t((12 / k) * d) << (12 * p + 4 * a);
                 }
             }
-            E |= uint64_t((prim >> 12) & 3) << 36 | uint64_t((prim >> 14) & 3) << 38;
+            const int u = (prim >> 12) & 3, wv = (prim >> 14) & 3;
+            E |= uint64_t(u) << 36 | uint64_t(wv) << 38 | uint64_t(cv[u]) << 40 | uint64_t(cv[wv]) << 43;
             t.ent[cell][e] = E;
         }
     }
@@ -446,7 +448,9 @@ __global__ __launch_bounds__(kBlock) void k_march_geometry(const int32_t* labels
     constexpr int kDim = THREE_D ? 3 : 2;
     __shared__ int32_t s_lab[kGeoWaves][kCorners][kWave];
     __shared__ uint32_t s_off[kGeoWaves][kWave + 1];
-    __shared__ uint32_t s_cnt[kGeoWaves][kWave];  // 4 bits per cell
+    // per cube: byte k = first primitive of cell k within the cube (k = 0..5),
+    // and byte k = cell k's first entry in the table
+    __shared__ uint64_t s_pre[kGeoWaves][kWave], s_bas[kGeoWaves][kWave];
     constexpr int kVals = kPts * kDim;              // floats per primitive
     __shared__ float s_xyz[kGeoWaves][kWave * kVals];
     __shared__ GeoTab s_tab;
@@ -485,7 +489,8 @@ __global__ __launch_bounds__(kBlock) void k_march_geometry(const int32_t* labels
             l[6] = gmem(p00 + plane + nx)[xc];
             l[7] = gmem(p00 + plane + nx)[xc + 1];
         }
-        uint32_t packed = 0, total = 0;
+        uint64_t pre = 0, bas = 0;
+        uint32_t total = 0;
 #pragma unroll
         for (int t = 0; t < kCells; ++t) {
             uint32_t code;
@@ -498,7 +503,8 @@ __global__ __launch_bounds__(kBlock) void k_march_geometry(const int32_t* labels
                 code = (b == a ? 0u : 4u) | (c == a ? 0u : c == b ? 1u : 2u);
             }
             const uint32_t m = valid ? uint32_t(s_tab.count[code]) : 0u;
-            packed |= m << (4 * t);
+            pre |= uint64_t(total) << (8 * t);
+            bas |= uint64_t(s_tab.base[code]) << (8 * t);
             total += m;
         }
         // exclusive scan of the cube totals over the wave
@@ -512,7 +518,8 @@ __global__ __launch_bounds__(kBlock) void k_march_geometry(const int32_t* labels
 #pragma unroll
         for (int i = 0; i < kCorners; ++i) s_lab[w][i][lane] = l[i];
         s_off[w][lane] = inc - total;
-        s_cnt[w][lane] = packed;
+        s_pre[w][lane] = pre;
+        s_bas[w][lane] = bas;
         if (lane == 0) s_off[w][kWave] = chunk;
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -524,36 +531,21 @@ __global__ __launch_bounds__(kBlock) void k_march_geometry(const int32_t* labels
 #pragma unroll
                 for (int step = kWave / 2; step > 0; step >>= 1)
                     if (s_off[w][c + step] <= i) c += step;
-                uint32_t rem = i - s_off[w][c];
-                const uint32_t pk = s_cnt[w][c];
-                int t = 0;  // the cell: skip the cells before it
-#pragma unroll
-                for (int q = 0; q < kCells - 1; ++q) {
-                    const uint32_t m = (pk >> (4 * q)) & 15u;
-                    const bool past = t == q && rem >= m;
-                    rem -= past ? m : 0u;
-                    t += past ? 1 : 0;
-                }
-                // the cell's vertices (corner indices) and their labels
-                int cv[4];
+                uint32_t rem = i - s_off[w][c];  // primitive within the cube (< 128)
+                const uint64_t pk = s_pre[w][c];
+                // the cell: how many of the cells 1..5 start at or before rem
+                // (four byte compares at once: no byte borrows, all are < 128)
+                int t;
                 if constexpr (THREE_D) {
-                    cv[0] = 0, cv[3] = 7;
-                    cv[1] = t == 0 || t == 1 ? 1 : t == 2 || t == 3 ? 2 : 4;
-                    cv[2] = t == 0 || t == 2 ? 3 : t == 1 || t == 4 ? 5 : 6;
+                    const uint32_t starts = uint32_t(pk >> 8);
+                    const uint32_t ge = (((rem * 0x01010101u) | 0x80808080u) - starts) & 0x80808080u;
+                    t = __builtin_popcount(ge) + (rem >= uint32_t(pk >> 40) ? 1 : 0);
                 } else {
-                    cv[0] = 0, cv[1] = t == 0 ? 1 : 2, cv[2] = 3, cv[3] = 3;
+                    t = rem >= uint32_t(pk >> 8) ? 1 : 0;
                 }
-                int32_t lab[4];
-#pragma unroll
-                for (int v = 0; v < 4; ++v) lab[v] = s_lab[w][cv[v]][c];
-                uint32_t code;
-                if constexpr (THREE_D)
-                    code = (lab[1] == lab[0] ? 0u : 16u) |
-                           ((lab[2] == lab[0] ? 0u : lab[2] == lab[1] ? 1u : 2u) << 2) |
-                           (lab[3] == lab[0] ? 0u : lab[3] == lab[1] ? 1u : lab[3] == lab[2] ? 2u : 3u);
-                else
-                    code = (lab[1] == lab[0] ? 0u : 4u) | (lab[2] == lab[0] ? 0u : lab[2] == lab[1] ? 1u : 2u);
-                const uint64_t e = s_tab.ent[t][s_tab.base[code] + rem];
+                rem -= uint32_t(pk >> (8 * t)) & 0xffu;
+                const uint32_t tb = uint32_t(s_bas[w][c] >> (8 * t)) & 0xffu;
+                const uint64_t e = s_tab.ent[t][tb + rem];
                 if (xyz) {
                     // a point: (12 * corner + its offset in twelfths) / 12,
                     // staged in LDS so that the wave's stores are contiguous
@@ -583,9 +575,9 @@ __global__ __launch_bounds__(kBlock) void k_march_geometry(const int32_t* labels
                 }
                 const uint64_t out = base + i;
                 if (sides && out < capacity) {
-                    const int u = int(e >> 36) & 3, v = int(e >> 38) & 3;
+                    const int cu = int(e >> 40) & 7, cw = int(e >> 43) & 7;
                     typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
-                    gmem(reinterpret_cast<i32x2*>(sides))[out] = i32x2{lab[u], lab[v]};
+                    gmem(reinterpret_cast<i32x2*>(sides))[out] = i32x2{s_lab[w][cu][c], s_lab[w][cw][c]};
                 }
             }
             if (xyz) {  // the staged points: consecutive lanes on consecutive floats
