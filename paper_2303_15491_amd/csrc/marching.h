@@ -434,10 +434,13 @@ __constant__ const GeoTab kGeoTab[4] = {make_geo_tab(false, 0), make_geo_tab(fal
 constexpr int kGeoWaves = kWavesPerBlock;
 
 // One wave per row of cubes; its lanes take 64 cubes at a time, count their
-// primitives, scan the counts over the wave, keep each cube's corner labels
-// and offset in LDS, and then write the chunk's primitives with consecutive
-// lanes on consecutive primitives (each lane finds its cube by a binary
-// search over the offsets, then its cell and its entry of the table).
+// primitives, scan the counts over the wave, keep each cube's corner labels,
+// offset, cell starts and table bases in LDS, and then write the chunk's
+// primitives with consecutive lanes on consecutive primitives: each lane
+// finds its cube by a binary search over the offsets, then its cell from the
+// cube's cell starts and its entry from the cell's table base.  The points of
+// 64 primitives are staged in LDS and stored by consecutive lanes on
+// consecutive floats.
 template <bool THREE_D, int MODE>
 __global__ __launch_bounds__(kBlock) void k_march_geometry(const int32_t* labels, int nx, int ny, uint32_t rows,
                                                            const uint64_t* row_offsets, uint64_t capacity,
