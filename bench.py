@@ -591,6 +591,19 @@ def main():
                                   cpu_planes=args.cpu_slab if field.ndim == 3 else 0)
     del ws, outs, field
     torch.cuda.empty_cache()
+    if marching is not None and f_host.ndim == 3:
+        # the triangle (2-D) kernels on a 4096^2 terrain-like field (smoothed
+        # noise, sigma 1.5): its MS labels through the same index and geometry
+        from paper_2303_15491_amd import fields as _fields
+
+        log("marching index and geometry on a 4096^2 field")
+        t2 = torch.from_numpy(_fields.smoothed_noise((4096, 4096), 1.5, seed=6)).to(dev)
+        seg = plmss.segment(t2)
+        torch.cuda.synchronize()
+        marching["planar_4096sq"] = bench_marching(torch, plmss, lib, seg["ms"], steps=args.steps, warmup=2,
+                                                   cpu_planes=0)
+        del t2, seg
+        torch.cuda.empty_cache()
     batched = None if args.no_batched else bench_batched(torch, plmss, steps=max(3, args.steps // 2), warmup=2)
     serving = bench_serving(torch, plmss, args.serve_requests, args.serve_rate) if args.serve_requests else None
     out = {

@@ -23,8 +23,16 @@
 
 namespace plmss {
 
-constexpr int kMarchRowsPerWave = 16;
+constexpr int kMarchRowsPerWave = 16;  // at most; fewer when a grid has few rows
 constexpr int kMarchRowsPerBlock = kMarchRowsPerWave * kWavesPerBlock;
+
+// Rows per wave of the count kernel: up to kMarchRowsPerWave, fewer when a
+// grid has few rows (a 2-D field), so that the launch still has about 4096
+// waves.
+inline int march_rows_per_wave(uint64_t rows) {
+    const uint64_t r = rows / 4096;
+    return r < 1 ? 1 : (r > uint64_t(kMarchRowsPerWave) ? kMarchRowsPerWave : int(r));
+}
 
 // Primitives of a cell from E, the number of its vertex pairs with equal
 // labels (equality is transitive, so E fixes how the labels split: for a
@@ -72,7 +80,7 @@ __device__ __forceinline__ uint64_t block_exclusive_u64(uint64_t x, uint64_t* tm
     return base + inc - x;
 }
 
-// Counts.  Each wave owns kMarchRowsPerWave consecutive rows; its lanes take
+// Counts.  Each wave owns rpw (<= kMarchRowsPerWave) consecutive rows; its lanes take
 // 64 consecutive cubes along x and walk the wave's rows in order, so that the
 // lower y face of a cube (corners 0, 1, 4, 5; bit 0 = +x, bit 1 = +y, bit 2 =
 // +z) and the label equalities on it come from the upper face of the same
@@ -87,14 +95,14 @@ __device__ __forceinline__ uint64_t block_exclusive_u64(uint64_t x, uint64_t* tm
 template <bool THREE_D, int MODE, bool CODES>
 __global__ __launch_bounds__(kBlock) void k_march_count(const int32_t* labels, int nx, int ny, uint32_t rows,
                                                         uint8_t* codes, uint64_t* row_offsets,
-                                                        uint64_t* block_sums) {
+                                                        uint64_t* block_sums, int rpw) {
     __shared__ uint64_t wsum[kWavesPerBlock];
     __shared__ uint32_t rcnt[kWavesPerBlock][kMarchRowsPerWave][kWave];
     const int lane = lane_id();
     const int w = __builtin_amdgcn_readfirstlane(wave_id());
     const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
-    const uint32_t r0 = b * kMarchRowsPerBlock + uint32_t(w) * kMarchRowsPerWave;
-    const int nrow = r0 < rows ? int(min<uint32_t>(kMarchRowsPerWave, rows - r0)) : 0;
+    const uint32_t r0 = (b * kWavesPerBlock + uint32_t(w)) * uint32_t(rpw);
+    const int nrow = r0 < rows ? int(min<uint32_t>(uint32_t(rpw), rows - r0)) : 0;
     const int ncube = nx - 1;
     const uint32_t ycubes = THREE_D ? uint32_t(ny - 1) : 0xffffffffu;
     const uint32_t y0 = THREE_D ? r0 % ycubes : r0, z0 = THREE_D ? r0 / ycubes : 0u;
@@ -247,14 +255,15 @@ __global__ __launch_bounds__(kBlock) void k_march_scan_blocks(uint64_t* block_su
     if (threadIdx.x == 0) *total = run;
 }
 
-// Row counts -> exclusive row offsets: block b's rows start at block_sums[b].
+// Row counts -> exclusive row offsets: block b's rows (rpb of them, as the
+// count kernel's block b) start at block_sums[b].
 __global__ __launch_bounds__(kBlock) void k_march_offsets(uint64_t* row_offsets, uint32_t rows,
-                                                          const uint64_t* block_sums) {
+                                                          const uint64_t* block_sums, int rpb) {
     __shared__ uint64_t tmp[kWavesPerBlock];
     static_assert(kMarchRowsPerBlock <= kBlock, "one row per thread");
     const uint32_t b = blockIdx.x;
-    const uint32_t r = b * kMarchRowsPerBlock + threadIdx.x;
-    const bool mine = threadIdx.x < kMarchRowsPerBlock && r < rows;
+    const uint32_t r = b * uint32_t(rpb) + threadIdx.x;
+    const bool mine = int(threadIdx.x) < rpb && r < rows;
     const uint64_t c = mine ? row_offsets[r] : 0ull;
     uint64_t tot;
     const uint64_t e = block_sums[b] + block_exclusive_u64(c, tmp, &tot);

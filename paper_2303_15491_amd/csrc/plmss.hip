@@ -184,9 +184,12 @@ int64_t march_rows(const plmss_dims& d) {
 }
 
 // One u64 per count block (its sum, then its first offset).
-size_t march_ws_bytes(uint64_t rows) {
-    return align_up(8 * std::max<uint64_t>(1, (rows + kMarchRowsPerBlock - 1) / kMarchRowsPerBlock), 256);
+uint64_t march_blocks(uint64_t rows) {
+    const uint64_t rpb = uint64_t(march_rows_per_wave(rows)) * kWavesPerBlock;
+    return (rows + rpb - 1) / rpb;
 }
+
+size_t march_ws_bytes(uint64_t rows) { return align_up(8 * std::max<uint64_t>(1, march_blocks(rows)), 256); }
 
 // ---- optional launch tracing -------------------------------------------------------------
 // While a trace is active on the calling host thread, every kernel launch is
@@ -960,13 +963,14 @@ int plmss_marching_index(const int32_t* labels, plmss_dims dims, int32_t mode, u
     if (!ws_ok(workspace, workspace_bytes, march_ws_bytes(rows))) return PLMSS_E_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     uint64_t* block_sums = static_cast<uint64_t*>(workspace);
-    const unsigned blocks = unsigned((rows + kMarchRowsPerBlock - 1) / kMarchRowsPerBlock);
+    const int rpw = march_rows_per_wave(rows);
+    const unsigned blocks = unsigned(march_blocks(rows));
     const int nx = int(dims.nx), ny = int(dims.ny);
     if (rows > 0)
         launch(PLMSS_KERNEL_MARCH, s, [&] {
             const int shape = (dims.nz > 1 ? 4 : 0) | (mode ? 2 : 0) | (codes ? 1 : 0);
             auto go = [&](auto kernel) {
-                kernel<<<blocks, kBlock, 0, s>>>(labels, nx, ny, uint32_t(rows), codes, row_offsets, block_sums);
+                kernel<<<blocks, kBlock, 0, s>>>(labels, nx, ny, uint32_t(rows), codes, row_offsets, block_sums, rpw);
             };
             switch (shape) {
                 case 0: go(k_march_count<false, 0, false>); break;
@@ -984,7 +988,7 @@ int plmss_marching_index(const int32_t* labels, plmss_dims dims, int32_t mode, u
     });
     if (rows > 0)
         launch(PLMSS_KERNEL_PREFIX, s, [&] {
-            k_march_offsets<<<blocks, kBlock, 0, s>>>(row_offsets, uint32_t(rows), block_sums);
+            k_march_offsets<<<blocks, kBlock, 0, s>>>(row_offsets, uint32_t(rows), block_sums, rpw * kWavesPerBlock);
         });
     return launch_status();
 }

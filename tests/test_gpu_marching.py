@@ -50,11 +50,12 @@ def _compare(torch, labels, mode, label=""):
     return ref
 
 
-# shapes (nz, ny, nx): ragged against the 64-cube lane chunks and the 16-row
-# wave / 64-row block split, one with more than 1024 count blocks (several
-# rounds of the block-sum scan), planar ones, and grids without cells
+# shapes (nz, ny, nx): ragged against the 64-cube lane chunks and the rows
+# per wave / per block split, ones with more than 1024 count blocks (several
+# rounds of the block-sum scan: 6000 rows at one row per wave), planar ones,
+# and grids without cells
 SHAPES_3D = [(2, 2, 2), (3, 5, 130), (4, 3, 65), (9, 17, 64), (5, 9, 66), (12, 9, 70), (3, 300, 300),
-             (2, 2, 4097)]
+             (2, 2, 4097), (2, 6001, 5)]
 SHAPES_2D = [(2, 2), (5, 130), (300, 257), (5000, 5), (1025, 65)]
 
 
@@ -76,6 +77,8 @@ def test_random_labels_2d(torch, k, mode):
 def test_many_blocks(torch, mode):
     _compare(torch, fields.random_labels(SHAPES_3D[6], 3, seed=7), mode, "3x300x300")
     _compare(torch, fields.region_labels(SHAPES_3D[7], seed=8), mode, "2x2x4097")
+    _compare(torch, fields.random_labels(SHAPES_3D[8], 3, seed=9), mode, "2x6001x5")
+    _compare(torch, fields.random_labels((70001, 3), 3, seed=10), mode, "70001x3")  # 16 rows per wave
 
 
 @pytest.mark.parametrize("shape", [(1, 1, 1), (7,), (3, 4, 1), (4, 1, 4), (4, 4, 1), (1, 1, 9), (2, 1, 1), (1, 6),
