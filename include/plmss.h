@@ -29,9 +29,10 @@
  *  - Labels are field-local int32 vertex ids.  MS ids run 0..K-1 in the
  *    lexicographic order of the (asc, desc) pair.
  *  - Every array argument is DEVICE memory owned by the caller unless stated
- *    otherwise.  The library never allocates device memory; scratch space is a
+ *    otherwise.  No call allocates device memory; scratch space is a
  *    caller-provided workspace of the size the matching *_workspace_bytes call
- *    returns.
+ *    returns (plmss_segment_static instead uses one fixed library-owned array
+ *    per GPU).
  *  - Every call is asynchronous on `stream` (a hipStream_t; NULL = the null
  *    stream).  The return value reports synchronous argument checks and launch
  *    errors only.  Data-dependent errors (NaN) are written on the device to
@@ -100,6 +101,28 @@ const char* plmss_build_info(void);
  */
 size_t plmss_workspace_bytes(plmss_dims dims, int32_t dtype, int32_t with_order);
 int plmss_segment(const plmss_job* job, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops and harnesses that forbid hipMalloc): the same
+ * segmentation as plmss_segment, with the same results, but without a
+ * workspace argument.  Its scratch space is one library-owned device array of
+ * plmss_static_scratch_bytes() bytes per GPU (the workspace of a field of
+ * PLMSS_STATIC_MAX_VERTICES vertices with its order field, about 60 MiB),
+ * created when the library is first used on that GPU and held until the
+ * process ends.  The call itself allocates nothing.  The caller still owns
+ * the field and every output (job, as for plmss_segment); the order field is
+ * always built on `stream`, before the labels.
+ * Every call on one GPU shares that GPU's array: two calls whose work
+ * overlaps on the same GPU (other streams, other host threads) race and give
+ * undefined results; calls on one stream are ordered and safe.  The array's
+ * contents on entry do not matter.
+ * Returns PLMSS_OK, PLMSS_E_ARG, PLMSS_E_DIMS, PLMSS_E_TOO_LARGE (also for
+ * N > PLMSS_STATIC_MAX_VERTICES) or PLMSS_E_HIP.
+ */
+#define PLMSS_STATIC_MAX_VERTICES (1 << 21)
+size_t plmss_static_scratch_bytes(void);
+int plmss_segment_static(const plmss_job* job, void* stream);
 
 /*
  * Step 0 alone -- the order field (paper, Sec. "Preprocessing"): sort the

@@ -13,7 +13,7 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["PlmssError", "library", "segment", "order_field", "steepest", "compress", "ms_ids",
+__all__ = ["PlmssError", "library", "segment", "segment_static", "STATIC_MAX_VERTICES", "order_field", "steepest", "compress", "ms_ids",
            "segment_batch", "workspace_bytes", "batch_workspace_bytes", "batch_needs", "Plan",
            "tune_get", "tune_set", "KNOBS", "marching_rows", "marching_index", "marching_geometry", "marching_geometry_union", "MARCH_SEPARATORS",
            "MARCH_BOUNDARIES"]
@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(_HERE, "libplmss.so")
 OK, E_ARG, E_DIMS, E_TOO_LARGE, E_NAN, E_WORKSPACE, E_HIP = 0, -1, -2, -3, -4, -5, -6
 F32, F64 = 0, 1
 MARCH_SEPARATORS, MARCH_BOUNDARIES = 0, 1
+STATIC_MAX_VERTICES = 1 << 21  # PLMSS_STATIC_MAX_VERTICES
 
 
 class PlmssError(RuntimeError):
@@ -50,6 +51,8 @@ _SIGNATURES = {
     "plmss_build_info": ([], ctypes.c_char_p),
     "plmss_workspace_bytes": ([Dims, ctypes.c_int32, ctypes.c_int32], ctypes.c_size_t),
     "plmss_segment": ([ctypes.POINTER(Job), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
+    "plmss_static_scratch_bytes": ([], ctypes.c_size_t),
+    "plmss_segment_static": ([ctypes.POINTER(Job), ctypes.c_void_p], ctypes.c_int),
     "plmss_order_workspace_bytes": ([Dims, ctypes.c_int32], ctypes.c_size_t),
     "plmss_order_field": ([ctypes.c_void_p, Dims, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                            ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
@@ -220,6 +223,30 @@ def segment(field, with_order: bool = False, workspace=None, stream=None, out=No
               out["ms"].data_ptr(), out["order"].data_ptr() if out.get("order") is not None else None,
               out["info"].data_ptr())
     _check(lib.plmss_segment(ctypes.byref(job), _ptr(ws), ws.numel(), _stream(stream)), "plmss_segment")
+    return out
+
+
+def _segment_outs(field, with_order):
+    torch = _torch()
+    out = {k: torch.empty(field.shape, dtype=torch.int32, device=field.device) for k in ("asc", "desc", "ms")}
+    if with_order:
+        out["order"] = torch.empty(field.shape, dtype=torch.int32, device=field.device)
+    out["info"] = torch.empty(4, dtype=torch.int32, device=field.device)
+    return out
+
+
+def segment_static(field, with_order: bool = False, stream=None, out=None):
+    """:func:`segment` without a workspace: the library's own per-GPU scratch
+    array is used (``plmss_segment_static``), so nothing is allocated but the
+    outputs (none at all when ``out`` is given).  Fields of at most
+    ``STATIC_MAX_VERTICES`` vertices; calls that overlap on one GPU race."""
+    code = _field_check(field)
+    if out is None:
+        out = _segment_outs(field, with_order)
+    job = Job(field.data_ptr(), dims_of(field.shape), code, out["asc"].data_ptr(), out["desc"].data_ptr(),
+              out["ms"].data_ptr(), out["order"].data_ptr() if out.get("order") is not None else None,
+              out["info"].data_ptr())
+    _check(library().plmss_segment_static(ctypes.byref(job), _stream(stream)), "plmss_segment_static")
     return out
 
 

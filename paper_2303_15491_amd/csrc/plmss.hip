@@ -48,7 +48,7 @@ unsigned persist_blocks() { return unsigned(knob(PLMSS_TUNE_PERSIST_BLOCKS)); }
 int scan_depth() { return int(knob(PLMSS_TUNE_SCAN_DEPTH)); }
 int scan_rounds() { return int(knob(PLMSS_TUNE_SCAN_ROUNDS)); }
 
-size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+constexpr size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 int bit_width(uint64_t x) {
     int b = 0;
@@ -120,12 +120,12 @@ struct Sizes {
 // id chunk (at most 2^31 / kChunk).
 constexpr size_t kSortAux = kRadix + (size_t(1) << (31 - kChunkBits));
 
-uint64_t n_tiles(uint64_t n) { return (n + kTile - 1) / kTile; }
+constexpr uint64_t n_tiles(uint64_t n) { return (n + kTile - 1) / kTile; }
 
 // nv vertices; table_stride > 0 reserves batch tables of that many entries per
 // range (all fields + 3 classes).
-Sizes work_sizes(uint64_t nv, uint64_t nfields, uint64_t table_stride) {
-    Sizes s;
+constexpr Sizes work_sizes(uint64_t nv, uint64_t nfields, uint64_t table_stride) {
+    Sizes s{};
     s.npad = align_up(std::max<uint64_t>(nv, 1), kBlock);
     s.keys = align_up(8 * s.npad, 256);
     s.vals = align_up(4 * s.npad, 256);
@@ -792,6 +792,36 @@ LaunchSet capacity_set(const Work& w, size_t stride, unsigned grid_s, unsigned g
 
 }  // namespace
 
+// ---- library-owned scratch for callers that cannot allocate ---------------------------------
+// One fixed array per GPU, sized for the workspace of a single field of up to
+// kStaticMaxVertices vertices, held until the process ends.  Host code never
+// takes the array's name as an address: it asks the runtime for the array's
+// address on the current device once (static_scratch) and uses that.
+constexpr uint64_t kStaticMaxVertices = PLMSS_STATIC_MAX_VERTICES;
+constexpr size_t kStaticScratchBytes = work_sizes(kStaticMaxVertices, 1, 0).total;
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+namespace {
+
+// The scratch array's device address on the current device; looked up once
+// per device, with that device current.  nullptr if the runtime fails.
+void* static_scratch() {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mutex;
+    static void* ptrs[kMaxDevices] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(mutex);
+    if (!ptrs[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        ptrs[dev] = p;
+    }
+    return ptrs[dev];
+}
+
+}  // namespace
+
 // ---- capacity plans (batched launches that a hipGraph can replay) -----------------------
 
 struct plmss_plan {
@@ -858,6 +888,26 @@ int plmss_segment(const plmss_job* job, void* workspace, size_t workspace_bytes,
         return rc != PLMSS_OK ? rc : launch_status();
     }
     run_set(L, job->field, job->order, uint32_t(n), w, s);
+    return launch_status();
+}
+
+size_t plmss_static_scratch_bytes(void) { return kStaticScratchBytes; }
+
+int plmss_segment_static(const plmss_job* job, void* stream) {
+    if (!job || !job->field || !job->asc || !job->desc || !job->ms) return PLMSS_E_ARG;
+    if (job->dtype != PLMSS_F32 && job->dtype != PLMSS_F64) return PLMSS_E_ARG;
+    uint64_t n;
+    int rc = check_dims(job->dims, &n);
+    if (rc) return rc;
+    if (n > kStaticMaxVertices) return PLMSS_E_TOO_LARGE;
+    const Sizes sz = work_sizes(n, 1, 0);
+    if (sz.total > kStaticScratchBytes) return PLMSS_E_TOO_LARGE;
+    void* ws = static_scratch();
+    if (!ws) return PLMSS_E_HIP;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // one half only: the order field, if asked for, is built on this stream
+    // before the labels (never on the concurrent stream, which needs a second half)
+    run_set(single_set(*job, n, scan_depth()), job->field, job->order, uint32_t(n), carve(ws, sz), s);
     return launch_status();
 }
 

@@ -63,6 +63,22 @@ def test_segment_argument_errors():
     assert seg(ctypes.byref(_job(4, 4, 1)), ctypes.c_void_p(FAKE + 4), need, None) == plmss.E_WORKSPACE
 
 
+def test_static_entry_point_argument_errors():
+    """plmss_segment_static checks its arguments and its size limit before it
+    touches the GPU (its scratch array is looked up only after them)."""
+    lib = plmss.library()
+    seg = lib.plmss_segment_static
+    assert seg(None, None) == plmss.E_ARG
+    assert seg(ctypes.byref(_job(4, 4, 1, field=None)), None) == plmss.E_ARG
+    assert seg(ctypes.byref(_job(4, 4, 1, dtype=3)), None) == plmss.E_ARG
+    assert seg(ctypes.byref(_job(0, 4, 1)), None) == plmss.E_DIMS
+    assert seg(ctypes.byref(_job(plmss.STATIC_MAX_VERTICES + 1, 1, 1)), None) == plmss.E_TOO_LARGE
+    assert seg(ctypes.byref(_job(256, 256, 33)), None) == plmss.E_TOO_LARGE
+    # the array holds the workspace of the largest accepted field
+    assert lib.plmss_static_scratch_bytes() >= lib.plmss_workspace_bytes(
+        plmss.Dims(plmss.STATIC_MAX_VERTICES, 1, 1), plmss.F64, 0)
+
+
 def test_step_entry_point_argument_errors():
     lib = plmss.library()
     d = plmss.Dims(8, 8, 8)
