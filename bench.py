@@ -29,9 +29,11 @@ HBM_PEAK_GBS = 8000.0
 # array the kernel is defined on is read once and written once (float32 field,
 # int32 labels, 32-bit keys).
 #   steepest      : read order or f (4), write up, dn (8)
-#   jump          : read up, dn (8), write asc, desc (8) and each vertex's
-#                   MS pair record index into ms (4); the listed pair records
-#                   (12 B per listed pair, about 7% of N) are left out
+#   jump          : read up, dn (8), write asc, desc (8).  Its other writes
+#                   are overhead, not counted: each vertex's MS pair record
+#                   index, kept in ms until the ids are known (4 B/vertex),
+#                   and the listed pair records (12 B per listed pair, about
+#                   7% of N)
 #   ms_final      : read slot (4), write ms (4)
 #   order_first   : read f (4), write key and id (8)
 #   order_scatter : read key and id (8), write key and id (8)  (a middle pass)
@@ -42,7 +44,7 @@ HBM_PEAK_GBS = 8000.0
 #                   [0]; read sorted ids (4), write order (4 / w) [w >= 2]
 #   order_regroup : read (id, position) (8), write it regrouped by id chunk (8)
 #   order_hist    : read key (4)
-ALGO_BYTES = {"steepest": 12.0, "jump": 20.0, "ms_final": 8.0, "order_first": 12.0, "order_scatter": 16.0,
+ALGO_BYTES = {"steepest": 12.0, "jump": 16.0, "ms_final": 8.0, "order_first": 12.0, "order_scatter": 16.0,
               "order_hist": 4.0, "order_regroup": 16.0}
 
 
@@ -79,29 +81,46 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def profiled_traffic(workload: str, kind: str, knobs: dict):
-    """HBM bytes per launch of `kind` from the committed rocprofv3 counter
-    summary of this workload, or (None, reason)."""
-    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
+# The kernel (as rocprofv3 names it) each trace kind launches on the headline
+# workload: one 3-D float32 field with its order field, default scan tiles.
+HEADLINE_SYMBOLS = {
+    "jump": "k_chase<JTile<32, 8, 8>, true>",
+    "steepest": "k_steepest<RankOrderPacked, 8, 16, true>",
+    "ms_final": "k_ms_final<JTile<32, 8, 8> >",
+    "order_scatter": "k_radix_scatter<PackedSrc, PackedDst>",
+    "order_first": "k_radix_scatter<FieldSrc<float, unsigned int>, PackedDst>",
+    "order_last": "k_rank_partition<PackedSrc>",
+    "order_regroup": "k_chunk_partition",
+    "order_invert": "k_invert_chunks",
+}
+
+
+def profile_entry(name: str, workload: str, kind: str, knobs: dict):
+    """The committed rocprofv3 summary `profiles/<name>_<workload>.md` row of
+    the kernel `kind` launches on this workload, or (None, reason).  A
+    summary holds only for the kernel sources and launch-shape knobs it was
+    taken with."""
+    path = os.path.join(ROOT, "profiles", f"{name}_{workload}.md")
     try:
         with open(path) as fh:
             text = fh.read()
     except OSError:
-        return None, "no counter profile for this workload"
+        return None, f"no {name} profile for this workload"
     start = text.find("```json")
     end = text.find("```", start + 7)
     if start < 0 or end < 0:
-        return None, "counter profile has no data block"
+        return None, f"{name} profile has no data block"
     data = json.loads(text[start + 7:end])
     if data.get("source_digest") != kernel_source_digest():
-        return None, "kernels changed since the counters were taken"
+        return None, "kernels changed since the profile was taken"
     for k in KIND_KNOBS.get(kind, ()):
         if data.get("knobs", {}).get(k) != knobs.get(k):
-            return None, f"counters were taken with {k}={data.get('knobs', {}).get(k)}, this run used {knobs.get(k)}"
-    entry = data.get("kinds", {}).get(kind)
+            return None, f"profile was taken with {k}={data.get('knobs', {}).get(k)}, this run used {knobs.get(k)}"
+    sym = HEADLINE_SYMBOLS.get(kind)
+    entry = data.get("symbols", {}).get(sym) if sym else None
     if not entry:
-        return None, f"no counters for {kind}"
-    return entry["hbm_bytes_per_launch"], path
+        return None, f"no profile row for {kind}"
+    return entry, os.path.relpath(path, ROOT)
 
 
 def log(msg):
@@ -135,17 +154,35 @@ def cpu_info():
     return model, os.cpu_count()
 
 
-def timed_region(step, steps, torch, lib=None, trace=None, max_launches=0):
+def step_stats(ms):
+    """The paper's protocol over per-step times (drop the best and the worst
+    run, average the rest) and the median."""
+    a = sorted(ms)
+    trimmed = a[1:-1] if len(a) > 2 else a
+    return {"trimmed_mean_ms": sum(trimmed) / len(trimmed), "median_ms": float(np.median(a)),
+            "min_ms": a[0], "max_ms": a[-1], "steps": len(a)}
+
+
+def timed_region(step, steps, torch, lib=None, trace=None, max_launches=0, per_step=None):
     """Runs `steps` steps between two device synchronisations; returns the wall
-    time in ms and (if traced) the per-launch (kind, ms) list."""
+    time in ms and (if traced) the per-launch (kind, ms) list.  per_step (a
+    list) receives each step's time from events recorded on the current
+    stream between the steps (the steps' work runs on that stream)."""
     torch.cuda.synchronize()
     if trace is not None:
         lib.plmss_trace_begin(trace)
+    events = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)] if per_step is not None else None
     t0 = time.perf_counter()
-    for _ in range(steps):
+    if events:
+        events[0].record()
+    for i in range(steps):
         step()
+        if events:
+            events[i + 1].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    if events:
+        per_step.extend(events[i].elapsed_time(events[i + 1]) for i in range(steps))
     launches = []
     if trace is not None:
         lib.plmss_trace_end(trace)
@@ -340,8 +377,12 @@ def bench_marching(torch, plmss, lib, labels, steps: int, warmup: int, cpu_plane
 
 def bench_batched(torch, plmss, steps: int, warmup: int):
     """The uneven batch (64 fields, sides 32..192): one plan launch (hipGraph)
-    against a loop of plain per-field calls that reads each field's K as a
-    caller would.  Both include everything from resident inputs to labels."""
+    against a loop of plain per-field calls, timed two ways with the same
+    synchronisation on both sides: launches only (one device synchronisation
+    after the whole batch), and with K read back as a caller would (the plain
+    loop reads each field's K after its call; the batch copies all of its
+    info words to the host once).  Both include everything from resident
+    inputs to labels."""
     from paper_2303_15491_amd import fields
 
     log("generating the uneven batch")
@@ -349,10 +390,21 @@ def bench_batched(torch, plmss, steps: int, warmup: int):
     dev = [torch.from_numpy(f).cuda() for f in host]
     nv = int(sum(f.size for f in host))
     ws = torch.empty(max(plmss.workspace_bytes(t.shape) for t in dev), dtype=torch.uint8, device="cuda")
-    outs_plain = [{k: torch.empty(t.shape, dtype=torch.int32, device="cuda") for k in ("asc", "desc", "ms")}
-                  | {"info": torch.empty(4, dtype=torch.int32, device="cuda")} for t in dev]
 
-    def plain():
+    def outs_with_infos():
+        infos = torch.zeros((len(dev), 4), dtype=torch.int32, device="cuda")
+        outs = [{k: torch.empty(t.shape, dtype=torch.int32, device="cuda") for k in ("asc", "desc", "ms")}
+                | {"info": infos[i]} for i, t in enumerate(dev)]
+        return outs, infos
+
+    outs_plain, _ = outs_with_infos()
+    outs_b, infos_b = outs_with_infos()
+
+    def plain_launches():
+        for t, o in zip(dev, outs_plain):
+            plmss.segment(t, workspace=ws, out=o)
+
+    def plain_read_k():
         for t, o in zip(dev, outs_plain):
             plmss.segment(t, workspace=ws, out=o)
             int(o["info"][3].item())  # the caller reads K
@@ -364,35 +416,39 @@ def bench_batched(torch, plmss, steps: int, warmup: int):
     tuned.pop("trials", None)
     needs = plmss.batch_needs(dev)
     plan = plmss.Plan(*needs)
-    outs_b = plan.set(dev)
+    plan.set(dev, outs=outs_b)
     plan.launch(graph=True)  # the graph keeps the tuned grids
     torch.cuda.synchronize()
     plmss.tune_set(**saved)  # the plain loop runs with the single-field settings
 
-    def batched():
+    def batched_launches():
         plan.set(dev, outs=outs_b)
         plan.launch(graph=True)
-        torch.cuda.synchronize()
+
+    def batched_read_k():
+        batched_launches()
+        infos_b.cpu()  # every field's K in one copy
 
     for _ in range(warmup):
-        plain()
-        batched()
+        plain_read_k()
+        batched_read_k()
     torch.cuda.synchronize()
     same = all(torch.equal(a[k], b[k]) for a, b in zip(outs_plain, outs_b) for k in ("asc", "desc", "ms", "info"))
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        plain()
-    torch.cuda.synchronize()
-    t_plain = (time.perf_counter() - t0) / steps
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        batched()
-    t_batch = (time.perf_counter() - t0) / steps
+    t_plain, _ = timed_region(plain_launches, steps, torch)
+    t_batch, _ = timed_region(batched_launches, steps, torch)
+    t_plain_k, _ = timed_region(plain_read_k, steps, torch)
+    t_batch_k, _ = timed_region(batched_read_k, steps, torch)
     plan.close()
+    t_plain, t_batch, t_plain_k, t_batch_k = (t / steps for t in (t_plain, t_batch, t_plain_k, t_batch_k))
     return {"workload": "64 fields, sides uniform in 32..192, sum of 16..256 Gaussians + N(0,0.02) (seeds 4+j)",
-            "vertices": nv, "batched_ms": t_batch * 1e3, "plain_loop_ms": t_plain * 1e3,
-            "batched_mvps": nv / t_batch / 1e6, "plain_loop_mvps": nv / t_plain / 1e6,
-            "speedup": t_plain / t_batch, "identical": bool(same), "tuned": tuned}
+            "vertices": nv, "batched_ms": t_batch, "plain_loop_ms": t_plain,
+            "batched_mvps": nv / t_batch / 1e3, "plain_loop_mvps": nv / t_plain / 1e3,
+            "speedup": t_plain / t_batch,
+            "timing": "launches only; one device synchronisation after all steps on each side",
+            "with_k_read": {"batched_ms": t_batch_k, "plain_loop_ms": t_plain_k, "speedup": t_plain_k / t_batch_k,
+                            "timing": "plain loop reads K after every field; the batch copies its info words "
+                                      "once"},
+            "identical": bool(same), "tuned": tuned}
 
 
 def bench_serving(torch, plmss, n_requests: int, rate: float):
@@ -524,9 +580,10 @@ def main():
     # same number of steps again with a HIP event pair around every launch
     # (the events add a little time of their own)
     log(f"timing {args.steps} full steps")
-    wall_full, _ = timed_region(step_full, args.steps, torch)
+    steps_full, steps_labels = [], []
+    wall_full, _ = timed_region(step_full, args.steps, torch, per_step=steps_full)
     log(f"timing {args.steps} label-only steps")
-    wall_labels, _ = timed_region(step_labels, args.steps, torch)
+    wall_labels, _ = timed_region(step_labels, args.steps, torch, per_step=steps_labels)
     log(f"timing {args.steps} full and {args.steps} label-only steps with per-kernel events")
     wall_full_traced, launches = timed_region(step_full, args.steps, torch, lib, trace, max_launches)
     wall_labels_traced, launches_l = timed_region(step_labels, args.steps, torch, lib, trace, max_launches)
@@ -550,10 +607,18 @@ def main():
         per_launch_bytes = None
         basis = "n/a"
     achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9 if per_launch_bytes else None
-    traffic, traffic_src = profiled_traffic(args.workload, dom, knobs)
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+    counters, traffic_src = profile_entry("hbm_traffic", args.workload, dom, knobs)
+    traffic = counters["hbm_bytes_per_dispatch"] if counters else None
+    stats, stats_src = profile_entry("kernel_stats", args.workload, dom, knobs)
+    rocprof_ms = stats["avg_us"] * 1e-3 if stats else None
+    roofline = {"bound": "hbm", "kernel": dom, "symbol": HEADLINE_SYMBOLS.get(dom), "achieved": achieved,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
                 "traffic_source": traffic_src, "avg_launch_ms": avg_ms,
+                "avg_launch_source": "HIP events around every launch of the kind, on its own stream, in this run",
+                "rocprof_avg_launch_ms": rocprof_ms, "rocprof_source": stats_src,
+                "frac_at_rocprof_time": (per_launch_bytes / (rocprof_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+                                         if rocprof_ms and per_launch_bytes else None),
                 "algorithmic_bytes_per_launch": per_launch_bytes, "basis": basis,
                 "kernel_source_digest": kernel_source_digest(),
                 "copy_probe_gbs": copy_gbs,
@@ -616,7 +681,11 @@ def main():
         "cpu_baseline": cpu,
         "tuned": tuned,
         "path_frac_of_hbm_roofline": n * 48.0 / (ms_step * 1e-3) / (HBM_PEAK_GBS * 1e9),
-        "labels_only": {"value": labels_value, "ms_per_step": ms_step_l,
+        "step_times": step_stats(steps_full),
+        "step_times_note": "per-step device times (events between steps): the mean of the middle runs "
+                           "(best and worst dropped, the paper's protocol) and the median; value and "
+                           "ms_per_step are the wall time over all timed steps",
+        "labels_only": {"value": labels_value, "ms_per_step": ms_step_l, "step_times": step_stats(steps_labels),
                         "path_frac_of_hbm_roofline": n * 48.0 / (ms_step_l * 1e-3) / (HBM_PEAK_GBS * 1e9),
                         "note": "same labels, order field not materialised (vertex order compared in place)"},
         "ms_per_step_traced": wall_full_traced / args.steps,

@@ -255,7 +255,10 @@ int plmss_marching_geometry(const int32_t* labels, plmss_dims dims, int32_t mode
  * plmss_segment on each job, computed by one launch per step over all fields
  * together.  jobs is a HOST array of n_jobs entries; the sum of their N must
  * be <= 2^31 - 1.  Order fields are not built in a batch (jobs[i].order must
- * be NULL).  One field's NaN only sets that job's info[0].
+ * be NULL).  One field's NaN only sets that job's info[0].  Asynchronous like
+ * every call: the descriptor table goes to the device through a page-locked
+ * staging buffer the library keeps (reused once its copy has completed), so
+ * the host neither waits for the batch nor needs to keep `jobs` alive.
  * Workspace: plmss_batch_workspace_bytes(n_jobs, jobs) bytes.
  */
 size_t plmss_batch_workspace_bytes(int32_t n_jobs, const plmss_job* jobs);
@@ -277,10 +280,11 @@ int32_t plmss_batch_needs(int32_t n_jobs, const plmss_job* jobs, int64_t* needs)
  *   plmss_plan_create   capacity (all > 0) and element type; NULL on failure.
  *   plmss_plan_workspace_bytes  device workspace the plan's calls need.
  *   plmss_plan_set      writes the batch's descriptor tables and totals into
- *                       the workspace (asynchronous copies on `stream`; waits
- *                       for earlier work on `stream` first, since it reuses
- *                       host staging buffers).  PLMSS_E_TOO_LARGE beyond the
- *                       capacity.  jobs[i].order must be NULL.
+ *                       the workspace (asynchronous copies on `stream`, staged
+ *                       through page-locked host buffers the library keeps;
+ *                       the call does not wait for the device).
+ *                       PLMSS_E_TOO_LARGE beyond the capacity.  jobs[i].order
+ *                       must be NULL.
  *   plmss_plan_launch   enqueues the kernels on `stream` (capturable).
  *   plmss_plan_launch_graph  the same through a hipGraph, captured on the
  *                       first call (and again when the workspace changes).

@@ -375,11 +375,28 @@ def marching_geometry(labels, mode: int = MARCH_SEPARATORS, with_xyz: bool = Tru
     dims = dims_of(labels.shape)
     three = dims.nz > 1
     pts = (3, 3) if three else (2, 2)
+    rows = int(library().plmss_marching_rows(dims))
+    if rows < 0:
+        raise PlmssError(E_DIMS, "plmss_marching_rows")
     if row_offsets is None:
         _, row_offsets = marching_index(labels, mode, with_codes=False, stream=stream)
+    elif (not row_offsets.is_cuda or row_offsets.dtype != torch.int64 or not row_offsets.is_contiguous()
+          or row_offsets.numel() < rows + 1):
+        raise ValueError("row_offsets must be a contiguous int64 device tensor of rows + 1 entries")
     if out is not None:
         xyz, sides, count = out
         count = int(count)
+        if count < 0:
+            raise ValueError("count (the output capacity) must be >= 0")
+        per_xyz = pts[0] * pts[1]
+        for name, t, dt, per in (("xyz", xyz, torch.float32, per_xyz), ("sides", sides, torch.int32, 2)):
+            if t is None:
+                continue
+            if not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous {dt} device tensor")
+            if t.numel() < count * per:
+                raise ValueError(f"{name} holds {t.numel()} elements, fewer than {count} primitives need "
+                                 f"({count * per})")
     else:
         count = int(row_offsets[-1].item())
         xyz = torch.empty((max(count, 1),) + pts, dtype=torch.float32, device=labels.device) if with_xyz else None

@@ -609,6 +609,72 @@ hipStream_t aux_stream() {
     return streams[dev];
 }
 
+// Host staging of the descriptor tables a batch call uploads: page-locked
+// buffers the library keeps for the life of the process.  A buffer is handed
+// out again only once the copy that last read it has completed (an event
+// recorded after the copy), so a call returns without waiting for the device.
+struct StageBuf {
+    void* host = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;
+    int device = -1;
+};
+
+// One host-to-device copy of a staged upload.
+struct Upload {
+    const void* src;
+    size_t bytes;
+    void* dst;
+};
+
+// Copies `parts` through one staging buffer on stream s.
+int staged_upload(const Upload* parts, int nparts, hipStream_t s) {
+    constexpr size_t kMaxBufs = 64;
+    static std::mutex mutex;
+    static std::vector<StageBuf> bufs;
+    size_t need = 0;
+    for (int i = 0; i < nparts; ++i) need += align_up(parts[i].bytes, 256);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return PLMSS_E_HIP;
+    std::lock_guard<std::mutex> lock(mutex);
+    StageBuf* b = nullptr;
+    for (StageBuf& c : bufs)
+        if (c.device == dev && c.bytes >= need && hipEventQuery(c.done) == hipSuccess) {
+            b = &c;
+            break;
+        }
+    if (!b && bufs.size() >= kMaxBufs) {
+        // every buffer is still being read: wait for the first large enough one
+        for (StageBuf& c : bufs)
+            if (c.device == dev && c.bytes >= need) {
+                if (hipEventSynchronize(c.done) != hipSuccess) return PLMSS_E_HIP;
+                b = &c;
+                break;
+            }
+        if (!b) return PLMSS_E_HIP;
+    }
+    if (!b) {
+        StageBuf c;
+        c.bytes = std::max<size_t>(align_up(need, 4096), 64 * 1024);
+        c.device = dev;
+        if (hipHostMalloc(&c.host, c.bytes) != hipSuccess) return PLMSS_E_HIP;
+        if (hipEventCreateWithFlags(&c.done, hipEventDisableTiming) != hipSuccess) {
+            (void)hipHostFree(c.host);
+            return PLMSS_E_HIP;
+        }
+        bufs.push_back(c);
+        b = &bufs.back();
+    }
+    uint8_t* h = static_cast<uint8_t*>(b->host);
+    for (int i = 0; i < nparts; ++i) {
+        std::memcpy(h, parts[i].src, parts[i].bytes);
+        if (hipMemcpyAsync(parts[i].dst, h, parts[i].bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+            return PLMSS_E_HIP;
+        h += align_up(parts[i].bytes, 256);
+    }
+    return hipEventRecord(b->done, s) == hipSuccess ? PLMSS_OK : PLMSS_E_HIP;
+}
+
 // One field with its order field: the order field is sorted on the auxiliary
 // stream (its own half of the workspace, wo) while the labels, which compare
 // the field values in place and so do not need it, run on s; s then waits for
@@ -833,8 +899,6 @@ struct plmss_plan {
     int bn = 1;
     int zc = 16;  // scan depth, fixed at creation: tables and launches agree
     Sizes sizes{};
-    FieldDesc* pinned = nullptr;     // host staging of the tables
-    uint32_t* pinned_tot = nullptr;  // host staging of the totals
     hipGraphExec_t exec = nullptr;
     void* graph_ws = nullptr;            // workspace the graph was captured with
     hipStream_t capture_stream = nullptr;  // private: capture never runs work
@@ -1087,13 +1151,11 @@ int plmss_segment_batch(int32_t n_jobs, const plmss_job* jobs, void* workspace,
     hipStream_t s = static_cast<hipStream_t>(stream);
     const Work w = carve(workspace, sz);
     const std::vector<FieldDesc> img = table_image(B, size_t(n_jobs));
-    if (hipMemcpyAsync(w.tables, img.data(), sizeof(FieldDesc) * img.size(), hipMemcpyHostToDevice, s) !=
-        hipSuccess)
-        return PLMSS_E_HIP;
+    const Upload part{img.data(), sizeof(FieldDesc) * img.size(), w.tables};
+    rc = staged_upload(&part, 1, s);
+    if (rc != PLMSS_OK) return rc;
     const LaunchSet L = batch_set(B, w.tables, size_t(n_jobs), jobs[0].dtype, id_bits(B.nv));
     run_set(L, nullptr, nullptr, 0, w, s);
-    // the host image must outlive the asynchronous copy
-    if (hipStreamSynchronize(s) != hipSuccess) return PLMSS_E_HIP;
     return launch_status();
 }
 
@@ -1125,16 +1187,6 @@ plmss_plan* plmss_plan_create(int64_t max_vertices, int32_t max_fields, int64_t 
     p->zc = scan_depth();
     p->sizes = work_sizes(uint64_t(max_vertices), uint64_t(max_fields),
                           uint64_t(max_fields));
-    if (hipHostMalloc(reinterpret_cast<void**>(&p->pinned), sizeof(FieldDesc) * 4 * size_t(max_fields)) !=
-        hipSuccess) {
-        delete p;
-        return nullptr;
-    }
-    if (hipHostMalloc(reinterpret_cast<void**>(&p->pinned_tot), 32 * sizeof(uint32_t)) != hipSuccess) {
-        (void)hipHostFree(p->pinned);
-        delete p;
-        return nullptr;
-    }
     return p;
 }
 
@@ -1142,8 +1194,6 @@ void plmss_plan_destroy(plmss_plan* p) {
     if (!p) return;
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
-    if (p->pinned) (void)hipHostFree(p->pinned);
-    if (p->pinned_tot) (void)hipHostFree(p->pinned_tot);
     delete p;
 }
 
@@ -1163,12 +1213,8 @@ int plmss_plan_set(plmss_plan* p, int32_t n_jobs, const plmss_job* jobs, void* w
     if (!ws_ok(workspace, workspace_bytes, p->sizes.total)) return PLMSS_E_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const Work w = carve(workspace, p->sizes);
-    // a launch still in flight may read the staging buffers: let it finish
-    if (hipStreamSynchronize(s) != hipSuccess) return PLMSS_E_HIP;
     const std::vector<FieldDesc> img = table_image(B, size_t(p->max_fields));
-    std::memcpy(p->pinned, img.data(), sizeof(FieldDesc) * img.size());
-    uint32_t* tot = p->pinned_tot;
-    std::memset(tot, 0, 32 * sizeof(uint32_t));
+    uint32_t tot[32] = {};
     for (int c = 0; c < kClasses; ++c) {
         tot[4 * c + 0] = B.s_tiles[c];
         tot[4 * c + 1] = B.j_tiles[c];
@@ -1176,12 +1222,9 @@ int plmss_plan_set(plmss_plan* p, int32_t n_jobs, const plmss_job* jobs, void* w
         tot[4 * c + 3] = B.region0[c];
     }
     tot[14] = uint32_t(n_jobs);
-    if (hipMemcpyAsync(w.tables, p->pinned, sizeof(FieldDesc) * img.size(), hipMemcpyHostToDevice, s) !=
-        hipSuccess)
-        return PLMSS_E_HIP;
-    if (hipMemcpyAsync(w.counters + kTot, tot, 32 * sizeof(uint32_t), hipMemcpyHostToDevice, s) != hipSuccess)
-        return PLMSS_E_HIP;
-    return PLMSS_OK;
+    const Upload parts[2] = {{img.data(), sizeof(FieldDesc) * img.size(), w.tables},
+                             {tot, sizeof(tot), w.counters + kTot}};
+    return staged_upload(parts, 2, s);
 }
 
 int plmss_plan_launch(plmss_plan* p, void* workspace, size_t workspace_bytes, void* stream) {

@@ -28,6 +28,25 @@ def _numel(r) -> int:
     return int(np.prod(r.shape))
 
 
+ADMIT, WAIT, REJECT_BATCH, REJECT_BUDGET = "admit", "wait", "reject: batch", "reject: budget"
+
+
+def admission(numel: int, nbytes: int, resident: int, queued: int, max_vertices: int, budget: int,
+              max_queued: int) -> str:
+    """What the server does with the request at the head of the queue: a
+    request that can never run (more vertices than one batch holds, or a
+    footprint above the whole budget) is rejected at once, so that it never
+    blocks the queue; one that does not fit next to the requests already
+    resident, or finds the upload queue full, waits; any other is admitted."""
+    if numel > max_vertices:
+        return REJECT_BATCH
+    if nbytes > budget:
+        return REJECT_BUDGET
+    if resident + nbytes > budget or queued >= max_queued:
+        return WAIT
+    return ADMIT
+
+
 class Request:
     __slots__ = ("rid", "host", "shape", "t_arrive", "t_admit", "t_launch", "t_done", "device", "out",
                  "event", "nbytes", "error", "staged")
@@ -93,12 +112,14 @@ class Server:
         torch = self.torch
         while self.pending:
             r = self.pending[0]
-            if _numel(r) > self.max_v:
+            verdict = admission(_numel(r), r.nbytes, self.resident, len(self.admitted), self.max_v, self.budget,
+                                4 * self.max_f)
+            if verdict == REJECT_BATCH or verdict == REJECT_BUDGET:
                 self.pending.popleft()
-                r.error = "too large for one batch"
+                r.error = "too large for one batch" if verdict == REJECT_BATCH else "larger than the memory budget"
                 self.rejected += 1
                 continue
-            if self.resident + r.nbytes > self.budget or len(self.admitted) >= 4 * self.max_f:
+            if verdict == WAIT:
                 break
             self.pending.popleft()
             self.resident += r.nbytes
@@ -127,6 +148,7 @@ class Server:
                     r.t_done = t
                     self.resident -= r.nbytes
                     r.device = None
+                    r.staged = None  # its upload finished before the batch ran
                     if not self.keep_results:
                         r.out = None
                     self.done.append(r)
@@ -170,6 +192,8 @@ class Server:
                     batch, fields = batch[:half], fields[:half]
             for r in batch:
                 stream.wait_event(r.event)
+                if r.event.query():
+                    r.staged = None  # the upload is done: drop the page-locked copy
             t = time.perf_counter()
             plan.launch(graph=True, stream=stream)
             ev = torch.cuda.Event()

@@ -18,15 +18,22 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_algorithmic_bytes():
-    assert bench.algo_bytes("jump", 1) == 20.0  # U, D read; desc, asc, record index written
+    assert bench.algo_bytes("jump", 1) == 16.0  # U, D read; desc, asc written (the record index is overhead)
     assert bench.algo_bytes("steepest", 1) == 12.0
     assert bench.algo_bytes("order_last", 1) == 16.0 and bench.algo_bytes("order_last", 2) == 12.0
     assert bench.algo_bytes("order_invert", 4) == 5.0
     assert bench.algo_bytes("radix_scatter", 1) is None
 
 
-def test_traffic_lookup_guards():
-    assert bench.profiled_traffic("no_such_workload", "jump", {})[0] is None
-    # a knob setting other than the profiled one yields no traffic figure
-    t, why = bench.profiled_traffic("c3", "jump", {"scan_depth": 8, "scan_rounds": 3})
-    assert t is None and why
+def test_profile_lookup_guards():
+    for name in ("hbm_traffic", "kernel_stats"):
+        assert bench.profile_entry(name, "no_such_workload", "jump", {})[0] is None
+        # a knob setting other than the profiled one yields no figure
+        t, why = bench.profile_entry(name, "c3", "jump", {"scan_depth": 8, "scan_rounds": 3})
+        assert t is None and why
+
+
+def test_step_stats_drop_best_and_worst():
+    st = bench.step_stats([5.0, 1.0, 2.0, 3.0, 100.0])
+    assert st["trimmed_mean_ms"] == 10.0 / 3 and st["median_ms"] == 3.0
+    assert st["min_ms"] == 1.0 and st["max_ms"] == 100.0

@@ -155,3 +155,45 @@ def test_grid3x3_orderings_in_one_batch(torch):
         assert o["desc"].cpu().numpy().ravel().tolist() == desc[i].tolist()
         assert o["ms"].cpu().numpy().ravel().tolist() == ms[i].tolist()
         assert int(o["info"][3]) == k[i]
+
+
+def _oracle_all(host_fields):
+    """Oracle segmentations of many fields, computed in parallel host threads
+    (each oracle call runs in C without the interpreter lock)."""
+    import concurrent.futures
+    import os
+
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with concurrent.futures.ThreadPoolExecutor(workers) as ex:
+        return list(ex.map(oracle.segment, host_fields))
+
+
+@pytest.mark.timeout(900)
+def test_full_uneven_batch_graph_against_oracle(torch):
+    """The whole 64-field uneven batch (sides 32..192, 16..256 Gaussians plus
+    noise) through a capacity plan replayed as a hipGraph, with the persistent
+    grid the batched measurement runs with, against the oracle field by field."""
+    saved = plmss.tune_get()
+    try:
+        plmss.tune_set(persist_blocks=4096)
+        _say("c4 generate")
+        host = fields.batch_fields(64, seed=4)
+        dev = [torch.from_numpy(f).cuda() for f in host]
+        plan = plmss.Plan(*plmss.batch_needs(dev))
+        _say("c4 plan launch (graph), twice")
+        outs = plan.set(dev)
+        plan.launch(graph=True)
+        plan.set(dev, outs=outs)
+        plan.launch(graph=True)
+        torch.cuda.synchronize()
+        _say("c4 oracle")
+        refs = _oracle_all(host)
+        for i, (ref, o) in enumerate(zip(refs, outs)):
+            info = o["info"].cpu().numpy()
+            assert info[0] == 0, i
+            for k in ("asc", "desc", "ms"):
+                np.testing.assert_array_equal(o[k].cpu().numpy(), ref[k], err_msg=f"c4 field {i} {k}")
+            assert (info[1], info[2], info[3]) == (ref["n_min"], ref["n_max"], ref["K"]), i
+        plan.close()
+    finally:
+        plmss.tune_set(**saved)

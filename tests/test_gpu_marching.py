@@ -251,6 +251,37 @@ def test_geometry_capacity_and_partial_outputs(torch):
     np.testing.assert_array_equal(only_sides.cpu().numpy(), ref["sides"])
 
 
+def test_geometry_rejects_bad_out_tensors(torch):
+    """Outputs smaller than the capacity, of the wrong type or layout, and
+    row offsets of the wrong type or length are refused before any launch."""
+    labels = _dev(torch, fields.random_labels((4, 5, 6), 3, seed=1))
+    _, offs = plmss.marching_index(labels, 0)
+    torch.cuda.synchronize()
+    cap = 10
+    ok_xyz = torch.empty((cap, 3, 3), dtype=torch.float32, device="cuda")
+    ok_sides = torch.empty((cap, 2), dtype=torch.int32, device="cuda")
+    bad = [
+        dict(out=(torch.empty((cap - 1, 3, 3), dtype=torch.float32, device="cuda"), ok_sides, cap)),
+        dict(out=(ok_xyz, torch.empty((cap - 1, 2), dtype=torch.int32, device="cuda"), cap)),
+        dict(out=(ok_xyz.double(), ok_sides, cap)),
+        dict(out=(ok_xyz, ok_sides.long(), cap)),
+        dict(out=(ok_xyz.cpu(), ok_sides, cap)),
+        dict(out=(torch.empty((3, 3, 2 * cap), dtype=torch.float32, device="cuda").transpose(0, 2), ok_sides, cap)),
+        dict(out=(ok_xyz, ok_sides, -1)),
+        dict(out=(ok_xyz, ok_sides, cap), row_offsets=offs.int()),
+        dict(out=(ok_xyz, ok_sides, cap), row_offsets=offs[:-1]),
+        dict(out=(ok_xyz, ok_sides, cap), row_offsets=offs.cpu()),
+    ]
+    for i, kw in enumerate(bad):
+        kw.setdefault("row_offsets", offs)
+        with pytest.raises(ValueError):
+            plmss.marching_geometry(labels, 0, **kw)
+            pytest.fail(f"case {i} was accepted")
+    # a null output of either kind is allowed
+    plmss.marching_geometry(labels, 0, row_offsets=offs, out=(None, ok_sides, cap))
+    torch.cuda.synchronize()
+
+
 def test_geometry_grids_without_cells(torch):
     for shape in [(1, 1, 1), (7,), (3, 4, 1), (4, 1, 4), (1, 6)]:
         labels = fields.random_labels(shape, 3, seed=2)
