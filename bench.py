@@ -440,6 +440,39 @@ def bench_batched(torch, plmss, steps: int, warmup: int):
     t_batch_k, _ = timed_region(batched_read_k, steps, torch)
     plan.close()
     t_plain, t_batch, t_plain_k, t_batch_k = (t / steps for t in (t_plain, t_batch, t_plain_k, t_batch_k))
+    # the same pair with every field's order field built on both sides
+    log("batched and plain loop with order fields")
+    plmss.tune_set(**tuned["knobs"])
+    plan_o = plmss.Plan(*needs, with_order=True)
+    outs_bo = plmss._outs_for(dev, with_order=True)
+    plan_o.set(dev, outs=outs_bo)
+    plan_o.launch(graph=True)
+    torch.cuda.synchronize()
+    plmss.tune_set(**saved)
+    ws_o = torch.empty(max(plmss.workspace_bytes(t.shape, with_order=True) for t in dev), dtype=torch.uint8,
+                       device="cuda")
+    outs_po = plmss._outs_for(dev, with_order=True)
+
+    def plain_order():
+        for t, o in zip(dev, outs_po):
+            plmss.segment(t, with_order=True, workspace=ws_o, out=o)
+
+    def batched_order():
+        plan_o.set(dev, outs=outs_bo)
+        plan_o.launch(graph=True)
+
+    for _ in range(warmup):
+        plain_order()
+        batched_order()
+    torch.cuda.synchronize()
+    same_o = all(torch.equal(a[k], b[k]) for a, b in zip(outs_po, outs_bo)
+                 for k in ("asc", "desc", "ms", "order", "info"))
+    t_plain_o, _ = timed_region(plain_order, steps, torch)
+    t_batch_o, _ = timed_region(batched_order, steps, torch)
+    t_plain_o, t_batch_o = t_plain_o / steps, t_batch_o / steps
+    plan_o.close()
+    del ws_o, outs_po, outs_bo
+    torch.cuda.empty_cache()
     return {"workload": "64 fields, sides uniform in 32..192, sum of 16..256 Gaussians + N(0,0.02) (seeds 4+j)",
             "vertices": nv, "batched_ms": t_batch, "plain_loop_ms": t_plain,
             "batched_mvps": nv / t_batch / 1e3, "plain_loop_mvps": nv / t_plain / 1e3,
@@ -448,12 +481,19 @@ def bench_batched(torch, plmss, steps: int, warmup: int):
             "with_k_read": {"batched_ms": t_batch_k, "plain_loop_ms": t_plain_k, "speedup": t_plain_k / t_batch_k,
                             "timing": "plain loop reads K after every field; the batch copies its info words "
                                       "once"},
+            "with_order_fields": {"batched_ms": t_batch_o, "plain_loop_ms": t_plain_o,
+                                  "batched_mvps": nv / t_batch_o / 1e3, "plain_loop_mvps": nv / t_plain_o / 1e3,
+                                  "speedup": t_plain_o / t_batch_o, "identical": bool(same_o),
+                                  "timing": "launches only, as above; every field's order field built"},
             "identical": bool(same), "tuned": tuned}
 
 
-def bench_serving(torch, plmss, n_requests: int, rate: float):
+def bench_serving(torch, plmss, n_requests: int, rate: float, saturate_rate: float):
     """Poisson arrivals of mixed 2-D (128^2..2048^2) and 3-D (64^3..384^3)
-    requests through the continuous-batching server, in real time."""
+    requests through the continuous-batching server, in real time: at the
+    workload's rate, and at a rate far above what the GPU sustains (its
+    capacity).  Beside them the plain loop over the same requests in arrival
+    order: upload, plmss_segment, wait, one request at a time."""
     from paper_2303_15491_amd import fields
     from paper_2303_15491_amd.serve import Server, run_trace
 
@@ -461,23 +501,62 @@ def bench_serving(torch, plmss, n_requests: int, rate: float):
     pool_n = 64
     _, pool_np = fields.serving_pool(pool_n, seed=5)
     pool = [torch.from_numpy(f).pin_memory() for f in pool_np]
-    trace = fields.serving_trace(n_requests, seed=5, rate=rate)
     sizes = [tuple(p.shape) for p in pool]
-    for i, req in enumerate(trace):  # every request is one of the pool's fields
-        req["shape"] = sizes[i % pool_n]
-    server = Server(budget_bytes=48 << 30, max_batch_vertices=64 << 20, max_batch_fields=32)
-    # warm-up: compile the graphs on a few requests
-    run_trace(server, trace[:16], lambda i, r: pool[i % pool_n], realtime=False)
-    server.done.clear()
-    log(f"serving {n_requests} requests at {rate}/s")
-    run_trace(server, trace, lambda i, r: pool[i % pool_n], realtime=True)
-    st = server.stats()
-    server.close()
-    offered = sum(int(np.prod(r["shape"])) for r in trace) / trace[-1]["t"] / 1e6
-    st.update({"rate_per_s": rate, "offered_mvps": offered,
-               "workload": "Poisson arrivals; half 2-D n^2 (n in 128..2048), half 3-D n^3 (n in 64..384), "
-                           "smoothed N(0,1) noise, sigma 1.5..4 (seed 5)"})
-    return st
+
+    def trace_at(r):
+        tr = fields.serving_trace(n_requests, seed=5, rate=r)
+        for i, req in enumerate(tr):  # every request is one of the pool's fields
+            req["shape"] = sizes[i % pool_n]
+        return tr
+
+    def served(r):
+        trace = trace_at(r)
+        server = Server(budget_bytes=48 << 30, max_batch_vertices=64 << 20, max_batch_fields=32)
+        # warm-up: compile the graphs on a few requests
+        run_trace(server, trace[:16], lambda i, q: pool[i % pool_n], realtime=False)
+        server.done.clear()
+        server.batch_sizes.clear()
+        log(f"serving {n_requests} requests at {r}/s")
+        run_trace(server, trace, lambda i, q: pool[i % pool_n], realtime=True)
+        st = server.stats()
+        server.close()
+        st.update({"rate_per_s": r,
+                   "offered_mvps": sum(int(np.prod(q["shape"])) for q in trace) / trace[-1]["t"] / 1e6})
+        return st
+
+    res = served(rate)
+    res["saturated"] = served(saturate_rate)
+    # the plain loop: one request after the other
+    log("plain per-request loop")
+    ws = torch.empty(max(plmss.workspace_bytes(s) for s in sizes), dtype=torch.uint8, device="cuda")
+    devbuf = [torch.empty(s, dtype=torch.float32, device="cuda") for s in sizes]
+    outs = [{k: torch.empty(s, dtype=torch.int32, device="cuda") for k in ("asc", "desc", "ms")}
+            | {"info": torch.empty(4, dtype=torch.int32, device="cuda")} for s in sizes]
+    order = [i % pool_n for i in range(n_requests)]
+    for i in order[:8]:
+        devbuf[i].copy_(pool[i], non_blocking=True)
+        plmss.segment(devbuf[i], workspace=ws, out=outs[i])
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for i in order:
+        t = time.perf_counter()
+        devbuf[i].copy_(pool[i], non_blocking=True)
+        plmss.segment(devbuf[i], workspace=ws, out=outs[i])
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t)
+    wall = time.perf_counter() - t0
+    verts = sum(int(np.prod(sizes[i])) for i in order)
+    res["plain_loop"] = {"requests": n_requests, "wall_s": wall, "throughput_mvps": verts / wall / 1e6,
+                         "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                         "timing": "upload from page-locked memory, plmss_segment, device synchronisation, per "
+                                   "request, back to back (no arrival gaps)"}
+    res["saturated_vs_plain_loop"] = res["saturated"]["throughput_mvps"] / res["plain_loop"]["throughput_mvps"]
+    res["workload"] = ("Poisson arrivals; half 2-D n^2 (n in 128..2048), half 3-D n^3 (n in 64..384), smoothed "
+                       "N(0,1) noise, sigma 1.5..4 (seed 5)")
+    del ws, devbuf, outs
+    torch.cuda.empty_cache()
+    return res
 
 
 def main():
@@ -491,6 +570,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the uneven-batch measurement")
     ap.add_argument("--serve-requests", type=int, default=2000, help="serving requests (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-saturate-rate", type=float, default=5000.0,
+                    help="arrival rate of the serving capacity run (far above what the GPU sustains)")
     ap.add_argument("--knobs", default=None,
                     help='launch-shape knobs as JSON (e.g. {"scan_depth": 8}); skips the autotuner')
     ap.add_argument("--no-float64", action="store_true", help="skip the float64 copy of the field")
@@ -670,7 +751,8 @@ def main():
         del t2, seg
         torch.cuda.empty_cache()
     batched = None if args.no_batched else bench_batched(torch, plmss, steps=max(3, args.steps // 2), warmup=2)
-    serving = bench_serving(torch, plmss, args.serve_requests, args.serve_rate) if args.serve_requests else None
+    serving = (bench_serving(torch, plmss, args.serve_requests, args.serve_rate, args.serve_saturate_rate)
+               if args.serve_requests else None)
     out = {
         "metric": METRIC, "value": value, "unit": "Mvertices/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",

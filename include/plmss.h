@@ -254,8 +254,11 @@ int plmss_marching_geometry(const int32_t* labels, plmss_dims dims, int32_t mode
  * Many fields of different sizes in one pass: the same results as calling
  * plmss_segment on each job, computed by one launch per step over all fields
  * together.  jobs is a HOST array of n_jobs entries; the sum of their N must
- * be <= 2^31 - 1.  Order fields are not built in a batch (jobs[i].order must
- * be NULL).  One field's NaN only sets that job's info[0].  Asynchronous like
+ * be <= 2^31 - 1.  Jobs with a non-NULL order get their order field (paper,
+ * Sec. "Preprocessing"): when any job asks for one, all the batch's vertices
+ * are sorted together by (job index, value, vertex id), so that each field's
+ * vertices fill one run of positions and each order field is its positions
+ * within that run.  One field's NaN only sets that job's info[0].  Asynchronous like
  * every call: the descriptor table goes to the device through a page-locked
  * staging buffer the library keeps (reused once its copy has completed), so
  * the host neither waits for the batch nor needs to keep `jobs` alive.
@@ -277,14 +280,17 @@ int32_t plmss_batch_needs(int32_t n_jobs, const plmss_job* jobs, int64_t* needs)
  * capacity and every total read on the device, so that one hipGraph captures
  * it once and replays it for any batch within the capacity (continuous
  * batching, serving).  Same results as plmss_segment per job.
- *   plmss_plan_create   capacity (all > 0) and element type; NULL on failure.
+ *   plmss_plan_create   capacity (all > 0), element type, and with_order (0 or
+ *                       1): whether the plan builds the order fields its jobs
+ *                       ask for (the graph then holds the order sort, run for
+ *                       every batch); NULL on failure.
  *   plmss_plan_workspace_bytes  device workspace the plan's calls need.
  *   plmss_plan_set      writes the batch's descriptor tables and totals into
  *                       the workspace (asynchronous copies on `stream`, staged
  *                       through page-locked host buffers the library keeps;
  *                       the call does not wait for the device).
- *                       PLMSS_E_TOO_LARGE beyond the capacity.  jobs[i].order
- *                       must be NULL.
+ *                       PLMSS_E_TOO_LARGE beyond the capacity; PLMSS_E_ARG for
+ *                       a job with an order field on a plan created without.
  *   plmss_plan_launch   enqueues the kernels on `stream` (capturable).
  *   plmss_plan_launch_graph  the same through a hipGraph, captured on the
  *                       first call (and again when the workspace changes).
@@ -292,7 +298,7 @@ int32_t plmss_batch_needs(int32_t n_jobs, const plmss_job* jobs, int64_t* needs)
  */
 typedef struct plmss_plan plmss_plan;
 plmss_plan* plmss_plan_create(int64_t max_vertices, int32_t max_fields, int64_t max_scan_tiles,
-                              int64_t max_chase_tiles, int32_t dtype);
+                              int64_t max_chase_tiles, int32_t dtype, int32_t with_order);
 void plmss_plan_destroy(plmss_plan* plan);
 size_t plmss_plan_workspace_bytes(const plmss_plan* plan);
 int plmss_plan_set(plmss_plan* plan, int32_t n_jobs, const plmss_job* jobs, void* workspace,

@@ -72,8 +72,8 @@ _SIGNATURES = {
     "plmss_segment_batch": ([ctypes.c_int32, ctypes.POINTER(Job), ctypes.c_void_p, ctypes.c_size_t,
                              ctypes.c_void_p], ctypes.c_int),
     "plmss_batch_needs": ([ctypes.c_int32, ctypes.POINTER(Job), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int32),
-    "plmss_plan_create": ([ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32],
-                          ctypes.c_void_p),
+    "plmss_plan_create": ([ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                           ctypes.c_int32], ctypes.c_void_p),
     "plmss_plan_destroy": ([ctypes.c_void_p], None),
     "plmss_plan_workspace_bytes": ([ctypes.c_void_p], ctypes.c_size_t),
     "plmss_plan_set": ([ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Job), ctypes.c_void_p, ctypes.c_size_t,
@@ -429,18 +429,34 @@ def marching_geometry_union(asc, desc, mode: int = MARCH_SEPARATORS, stream=None
 
 
 def _jobs(fields, outs):
+    torch = _torch()
     arr = (Job * len(fields))()
     for i, (f, o) in enumerate(zip(fields, outs)):
+        for k in ("asc", "desc", "ms", "order"):
+            t = o.get(k)
+            if t is None and k == "order":
+                continue
+            if (t is None or not t.is_cuda or t.dtype != torch.int32 or not t.is_contiguous()
+                    or t.numel() != f.numel()):
+                raise ValueError(f"output {k} of field {i} must be a contiguous int32 device tensor of its size")
+        info = o.get("info")
+        if info is not None and (not info.is_cuda or info.dtype != torch.int32 or not info.is_contiguous()
+                                 or info.numel() < 4):
+            raise ValueError(f"info of field {i} must be a contiguous int32 device tensor of 4 entries")
+        order = o.get("order")
         arr[i] = Job(f.data_ptr(), dims_of(f.shape), _dtype_code(f), o["asc"].data_ptr(), o["desc"].data_ptr(),
-                     o["ms"].data_ptr(), None, o["info"].data_ptr())
+                     o["ms"].data_ptr(), order.data_ptr() if order is not None else None,
+                     info.data_ptr() if info is not None else None)
     return arr
 
 
-def _outs_for(fields):
+def _outs_for(fields, with_order=False):
     torch = _torch()
     outs = []
     for f in fields:
         o = {k: torch.empty(f.shape, dtype=torch.int32, device=f.device) for k in ("asc", "desc", "ms")}
+        if with_order:
+            o["order"] = torch.empty(f.shape, dtype=torch.int32, device=f.device)
         o["info"] = torch.empty(4, dtype=torch.int32, device=f.device)
         outs.append(o)
     return outs
@@ -463,13 +479,14 @@ def batch_workspace_bytes(fields) -> int:
     return int(library().plmss_batch_workspace_bytes(len(fields), arr))
 
 
-def segment_batch(fields, workspace=None, stream=None, outs=None):
+def segment_batch(fields, with_order: bool = False, workspace=None, stream=None, outs=None):
     """Segment many device fields of any sizes in one pass; returns one dict
-    per field as :func:`segment` does (without ``order``)."""
+    per field as :func:`segment` does (with ``order`` when ``with_order``;
+    given ``outs``, the fields whose dict holds an ``order`` tensor get it)."""
     for f in fields:
         _field_check(f)
     if outs is None:
-        outs = _outs_for(fields)
+        outs = _outs_for(fields, with_order)
     arr = _jobs(fields, outs)
     lib = library()
     nbytes = lib.plmss_batch_workspace_bytes(len(fields), arr)
@@ -485,12 +502,13 @@ class Plan:
     replayable hipGraph (see ``plmss_plan_*`` in plmss.h)."""
 
     def __init__(self, max_vertices: int, max_fields: int, max_scan_tiles: int, max_chase_tiles: int,
-                 dtype=None, device="cuda"):
+                 dtype=None, device="cuda", with_order: bool = False):
         torch = _torch()
         code = F64 if dtype == torch.float64 else F32
         self._lib = library()
+        self.with_order = bool(with_order)
         self._h = self._lib.plmss_plan_create(int(max_vertices), int(max_fields), int(max_scan_tiles),
-                                              int(max_chase_tiles), code)
+                                              int(max_chase_tiles), code, int(self.with_order))
         if not self._h:
             raise PlmssError(E_ARG, "plmss_plan_create")
         nbytes = self._lib.plmss_plan_workspace_bytes(self._h)
@@ -498,11 +516,12 @@ class Plan:
         self._jobs = None
 
     def set(self, fields, outs=None, stream=None):
-        """Points the plan at a batch; returns the output dicts."""
+        """Points the plan at a batch; returns the output dicts (with an
+        ``order`` tensor each when the plan builds order fields)."""
         for f in fields:
             _field_check(f)
         if outs is None:
-            outs = _outs_for(fields)
+            outs = _outs_for(fields, self.with_order)
         self._jobs = _jobs(fields, outs)  # kept alive with the tables
         self._fields, self._outs = fields, outs
         _check(self._lib.plmss_plan_set(self._h, len(fields), self._jobs, _ptr(self.workspace),

@@ -13,6 +13,7 @@
 
 #include "common.h"
 #include "marching.h"
+#include "order_batch.h"
 #include "segment.h"
 #include "sort.h"
 
@@ -300,11 +301,14 @@ struct SplitItems {
 
 // Last pass of the order field and the inversion by id chunks: the last
 // pass writes (id, position) pairs grouped by id range to parts,
-// k_chunk_partition regroups them by chunk into parts2, k_invert_chunks
-// writes each chunk of order[] from LDS.
+// k_chunk_partition regroups them by chunk into parts2, and the chunks are
+// inverted in LDS: into `order` (one field), or through the descriptors of
+// `batch` into each field's order array (batch != nullptr).  cnt: the length
+// on the device (capacity launches; the grids are sized for n), or nullptr.
 template <class Src>
-void invert_by_chunks(Src src, uint32_t n, unsigned workers, int last, uint64_t* parts, uint64_t* parts2,
-                      int32_t* order, const Work& w, int32_t* info, hipStream_t s) {
+void invert_by_chunks(Src src, const uint32_t* cnt, uint32_t n, unsigned workers, int last, uint64_t* parts,
+                      uint64_t* parts2, int32_t* order, const Fields* batch, const Work& w, int32_t* info,
+                      hipStream_t s) {
     // id ranges of 1 to 256 chunks, at most 64 of them below 2^29 vertices
     // (longer write runs) and 256 above; ihist (256 x workers <= npad
     // entries) in rank_of, which the order sort does not otherwise use
@@ -315,23 +319,27 @@ void invert_by_chunks(Src src, uint32_t n, unsigned workers, int last, uint64_t*
     uint32_t* chunk_fill = w.sortaux + kRadix;
     const uint32_t chunks = uint32_t((uint64_t(n) + kChunk - 1) / kChunk);
     launch(PLMSS_KERNEL_ORDER_HIST, s, [&] {
-        k_radix_hist<Src, false, true><<<workers, kBlock, 0, s>>>(src, nullptr, n, last, w.hist, info, id_shift,
+        k_radix_hist<Src, false, true><<<workers, kBlock, 0, s>>>(src, cnt, n, last, w.hist, info, id_shift,
                                                                   ihist);
     });
     digit_scan(w.hist, w.dtotal, workers, w, s);
     digit_scan(ihist, itotal, workers, w, s);
     launch(PLMSS_KERNEL_ORDER_LAST, s, [&] {
-        k_rank_partition<Src><<<workers, kBlock, 0, s>>>(src, n, last, w.hist, w.dtotal, ihist, itotal, id_shift,
-                                                         parts);
+        k_rank_partition<Src><<<workers, kBlock, 0, s>>>(src, cnt, n, last, w.hist, w.dtotal, ihist, itotal,
+                                                         id_shift, parts);
     });
     launch(PLMSS_KERNEL_MISC, s, [&] {
         k_zero_u32<<<std::min(256u, (chunks + kBlock - 1) / kBlock), kBlock, 0, s>>>(chunk_fill, chunks);
     });
     launch(PLMSS_KERNEL_ORDER_REGROUP, s, [&] {
-        k_chunk_partition<<<tiles, kBlock, 0, s>>>(parts, n, id_shift, chunk_fill, parts2);
+        k_chunk_partition<<<tiles, kBlock, 0, s>>>(parts, cnt, n, id_shift, chunk_fill, parts2);
     });
-    launch(PLMSS_KERNEL_ORDER_INVERT, s,
-           [&] { k_invert_chunks<<<chunks, kInvertBlock, 0, s>>>(parts2, n, order); });
+    if (batch)
+        launch(PLMSS_KERNEL_ORDER_INVERT, s,
+               [&] { k_invert_chunks_batch<<<chunks, kInvertBlock, 0, s>>>(parts2, cnt, n, *batch); });
+    else
+        launch(PLMSS_KERNEL_ORDER_INVERT, s,
+               [&] { k_invert_chunks<<<chunks, kInvertBlock, 0, s>>>(parts2, n, order); });
 }
 
 // The passes of an order sort after its first: middle passes at shifts
@@ -362,7 +370,8 @@ void order_tail(const Items& it, int cur, int first_shift, int last, uint32_t n,
     if (inv == 1) {
         // the pairs go to it.spare(cur); it.own(cur) is free once the last
         // pass has read it
-        invert_by_chunks(it.src(cur), n, workers, last, it.spare(cur), it.own(cur), order, w, info, s);
+        invert_by_chunks(it.src(cur), nullptr, n, workers, last, it.spare(cur), it.own(cur), order, nullptr, w,
+                         info, s);
         return;
     }
     const auto src = it.last_src(cur);
@@ -447,6 +456,50 @@ void order_any(const void* field, int32_t dtype, uint32_t n, int32_t* order, con
         sort_order<double, uint64_t>(static_cast<const double*>(field), n, order, w, info, s);
 }
 
+// Order fields of every field of a batch (order_batch.h): one sort of all the
+// batch's vertices by (field index, key, id).  n: the vertices the grids are
+// sized for (a capacity when cnt points to the batch's own total on the
+// device); max_fields bounds the field indices.
+template <typename T>
+void order_batch_sort(const Fields& all, const uint32_t* cnt, uint32_t n, uint32_t max_fields, const Work& w,
+                      hipStream_t s) {
+    const unsigned tiles = unsigned(n_tiles(n));
+    const unsigned workers = order_workers(n);
+    uint64_t* kv0 = reinterpret_cast<uint64_t*>(w.keys[0]);
+    uint64_t* kv1 = reinterpret_cast<uint64_t*>(w.keys[1]);
+    launch(PLMSS_KERNEL_ORDER_FIRST, s, [&] { k_batch_keys<T><<<tiles, kBlock, 0, s>>>(all, cnt, n, kv0, w.vals[0]); });
+    const PackedItems pk{{kv0, kv1}, w.vals[1], w.npad};
+    int cur = 0;
+    if constexpr (sizeof(T) == 8) {
+        // 64-bit keys: the low four digits as a key array and an id array,
+        // the fourth pass packing each key's high half with its id
+        const SplitItems<uint64_t> sp{{kv0, kv1}, {w.vals[0], w.vals[1]}};
+        radix_pass(sp.src(0), sp.dst(1), cnt, n, workers, 0, false, w, nullptr, s, kOrderKinds);
+        radix_pass(sp.src(1), sp.dst(0), cnt, n, workers, kRadixBits, false, w, nullptr, s, kOrderKinds);
+        radix_pass(sp.src(0), sp.dst(1), cnt, n, workers, 2 * kRadixBits, false, w, nullptr, s, kOrderKinds);
+        radix_pass(sp.src(1), HighPackedDst{kv0}, cnt, n, workers, 3 * kRadixBits, false, w, nullptr, s,
+                   kOrderKinds);
+    }
+    for (int shift = 0; shift < 32; shift += kRadixBits) {
+        // the last key pass stores each item's field index in place of its key
+        if (shift + kRadixBits < 32)
+            radix_pass(pk.src(cur), pk.dst(cur ^ 1), cnt, n, workers, shift, false, w, nullptr, s, kOrderKinds);
+        else
+            radix_pass(pk.src(cur), PackedFieldDst{pk.kv[cur ^ 1], all}, cnt, n, workers, shift, false, w, nullptr,
+                       s, kOrderKinds);
+        cur ^= 1;
+    }
+    // the field index, most significant, one digit per pass
+    const int fpasses = (std::max(1, bit_width(uint64_t(max_fields) - 1)) + kRadixBits - 1) / kRadixBits;
+    for (int p = 0; p + 1 < fpasses; ++p) {
+        radix_pass(pk.src(cur), pk.dst(cur ^ 1), cnt, n, workers, kRadixBits * p, false, w, nullptr, s,
+                   kOrderKinds);
+        cur ^= 1;
+    }
+    invert_by_chunks(pk.src(cur), cnt, n, workers, kRadixBits * (fpasses - 1), pk.spare(cur), pk.own(cur), nullptr,
+                     &all, w, nullptr, s);
+}
+
 // Sorts the listed (asc, desc) pair keys (keys[1], record indices in vals[0];
 // the count in counters[0], known only on the device).
 struct PairList {
@@ -477,6 +530,10 @@ struct LaunchSet {
     bool used[kClasses];
     unsigned grid_s[kClasses], grid_j[kClasses];
     bool capacity;                // grids sized for a capacity, totals on the device
+    bool batch_order;             // build the order fields of a batch's jobs
+    uint32_t nv;                  // vertices of the launch (its capacity when `capacity`)
+    const uint32_t* nv_dev;       // the launch's own total on the device (capacity launches)
+    uint32_t max_fields;          // fields of the launch (its capacity when `capacity`)
     int bn;
     int32_t dtype;
     int zc;                       // scan depth of the 3-D scan tiles
@@ -589,7 +646,12 @@ void labels_set(const LaunchSet& L, const int32_t* order, const Work& w, hipStre
 void run_set(const LaunchSet& L, const void* field, int32_t* order, uint32_t n_single, const Work& w,
              hipStream_t s) {
     init_set(L, w, s);
-    if (order) order_any(field, L.dtype, n_single, order, w, L.all.one.info, s);
+    if (order)
+        order_any(field, L.dtype, n_single, order, w, L.all.one.info, s);
+    else if (L.batch_order && L.dtype == PLMSS_F32)
+        order_batch_sort<float>(L.all, L.nv_dev, L.nv, L.max_fields, w, s);
+    else if (L.batch_order)
+        order_batch_sort<double>(L.all, L.nv_dev, L.nv, L.max_fields, w, s);
     labels_set(L, order, w, s);
 }
 
@@ -711,6 +773,7 @@ FieldDesc desc_of(const plmss_job& j, uint32_t vbase, uint32_t sbase, uint32_t j
     d.desc = j.desc;
     d.ms = j.ms;
     d.info = j.info;
+    d.order = j.order;
     d.nx = int32_t(j.dims.nx);
     d.ny = int32_t(j.dims.ny);
     d.nz = int32_t(j.dims.nz);
@@ -746,6 +809,10 @@ LaunchSet single_set(const plmss_job& job, uint64_t n, int zc) {
     L.grid_s[c] = st;
     L.grid_j[c] = jt;
     L.capacity = false;
+    L.batch_order = false;
+    L.nv = uint32_t(n);
+    L.nv_dev = nullptr;
+    L.max_fields = 1;
     L.bn = id_bits(n);
     L.dtype = job.dtype;
     return L;
@@ -758,6 +825,7 @@ struct BatchLayout {
     uint32_t s_tiles[kClasses] = {0, 0, 0}, j_tiles[kClasses] = {0, 0, 0}, region0[kClasses] = {0, 0, 0};
     uint64_t nv = 0, regions = 0;
     int zc = 16;
+    bool with_order = false;  // some job asks for its order field
 };
 
 int batch_layout(int32_t n_jobs, const plmss_job* jobs, int zc, BatchLayout* B) {
@@ -767,7 +835,8 @@ int batch_layout(int32_t n_jobs, const plmss_job* jobs, int zc, BatchLayout* B) 
     std::vector<uint64_t> nvert(n_jobs);
     for (int32_t i = 0; i < n_jobs; ++i) {
         const plmss_job& j = jobs[i];
-        if (!j.field || !j.asc || !j.desc || !j.ms || j.order) return PLMSS_E_ARG;
+        if (!j.field || !j.asc || !j.desc || !j.ms) return PLMSS_E_ARG;
+        B->with_order |= j.order != nullptr;
         if (j.dtype != PLMSS_F32 && j.dtype != PLMSS_F64) return PLMSS_E_ARG;
         if (j.dtype != dtype) return PLMSS_E_ARG;
         int rc = check_dims(j.dims, &nvert[i]);
@@ -820,6 +889,10 @@ LaunchSet batch_set(const BatchLayout& B, const FieldDesc* tables, size_t stride
         L.grid_j[c] = B.j_tiles[c];
     }
     L.capacity = false;
+    L.batch_order = B.with_order;
+    L.nv = uint32_t(B.nv);
+    L.nv_dev = nullptr;
+    L.max_fields = uint32_t(B.all.size());
     L.bn = bn;
     L.dtype = dtype;
     L.zc = B.zc;
@@ -828,11 +901,11 @@ LaunchSet batch_set(const BatchLayout& B, const FieldDesc* tables, size_t stride
 
 // Device totals block of a capacity launch (u32, in counters[32..63]):
 //   [4c .. 4c+3]  class c: scan tiles, chase tiles, fields, first region
-//   [12 .. 15]    all fields: 0, 0, fields, 0
+//   [12 .. 15]    all fields: 0, vertices, fields, 0
 constexpr int kTot = 32;
 
 LaunchSet capacity_set(const Work& w, size_t stride, unsigned grid_s, unsigned grid_j, int32_t dtype, int bn,
-                       int zc) {
+                       int zc, bool with_order, uint32_t max_vertices) {
     const uint32_t* tot = w.counters + kTot;
     LaunchSet L{};
     L.all = Fields{};
@@ -850,6 +923,10 @@ LaunchSet capacity_set(const Work& w, size_t stride, unsigned grid_s, unsigned g
         L.grid_j[c] = grid_j;
     }
     L.capacity = true;
+    L.batch_order = with_order;
+    L.nv = max_vertices;
+    L.nv_dev = tot + 13;
+    L.max_fields = uint32_t(stride);
     L.bn = bn;
     L.dtype = dtype;
     L.zc = zc;
@@ -896,6 +973,7 @@ struct plmss_plan {
     int64_t max_scan_tiles = 0;
     int64_t max_chase_tiles = 0;
     int32_t dtype = 0;
+    bool with_order = false;  // the plan builds the order fields its jobs ask for
     int bn = 1;
     int zc = 16;  // scan depth, fixed at creation: tables and launches agree
     Sizes sizes{};
@@ -1172,9 +1250,9 @@ int32_t plmss_batch_needs(int32_t n_jobs, const plmss_job* jobs, int64_t* needs)
 }
 
 plmss_plan* plmss_plan_create(int64_t max_vertices, int32_t max_fields, int64_t max_scan_tiles,
-                              int64_t max_chase_tiles, int32_t dtype) {
+                              int64_t max_chase_tiles, int32_t dtype, int32_t with_order) {
     if (max_vertices < 1 || max_vertices > kMaxN || max_fields < 1 || max_scan_tiles < 1 ||
-        max_chase_tiles < 1 || (dtype != PLMSS_F32 && dtype != PLMSS_F64))
+        max_chase_tiles < 1 || (dtype != PLMSS_F32 && dtype != PLMSS_F64) || (with_order != 0 && with_order != 1))
         return nullptr;
     plmss_plan* p = new (std::nothrow) plmss_plan;
     if (!p) return nullptr;
@@ -1183,6 +1261,7 @@ plmss_plan* plmss_plan_create(int64_t max_vertices, int32_t max_fields, int64_t 
     p->max_scan_tiles = max_scan_tiles;
     p->max_chase_tiles = max_chase_tiles;
     p->dtype = dtype;
+    p->with_order = with_order != 0;
     p->bn = id_bits(uint64_t(max_vertices));
     p->zc = scan_depth();
     p->sizes = work_sizes(uint64_t(max_vertices), uint64_t(max_fields),
@@ -1206,6 +1285,7 @@ int plmss_plan_set(plmss_plan* p, int32_t n_jobs, const plmss_job* jobs, void* w
     int rc = batch_layout(n_jobs, jobs, p->zc, &B);
     if (rc) return rc;
     if (jobs[0].dtype != p->dtype) return PLMSS_E_ARG;
+    if (B.with_order && !p->with_order) return PLMSS_E_ARG;
     if (n_jobs > p->max_fields || B.nv > uint64_t(p->max_vertices) ||
         B.regions > uint64_t(p->max_chase_tiles) ||
         uint64_t(B.s_tiles[0]) + B.s_tiles[1] + B.s_tiles[2] > uint64_t(p->max_scan_tiles))
@@ -1221,6 +1301,7 @@ int plmss_plan_set(plmss_plan* p, int32_t n_jobs, const plmss_job* jobs, void* w
         tot[4 * c + 2] = uint32_t(B.cls[c].size());
         tot[4 * c + 3] = B.region0[c];
     }
+    tot[13] = uint32_t(B.nv);
     tot[14] = uint32_t(n_jobs);
     const Upload parts[2] = {{img.data(), sizeof(FieldDesc) * img.size(), w.tables},
                              {tot, sizeof(tot), w.counters + kTot}};
@@ -1234,8 +1315,8 @@ int plmss_plan_launch(plmss_plan* p, void* workspace, size_t workspace_bytes, vo
     const Work w = carve(workspace, p->sizes);
     const unsigned gs = unsigned(std::min<int64_t>(persist_blocks(), p->max_scan_tiles));
     const unsigned gj = unsigned(std::min<int64_t>(persist_blocks(), p->max_chase_tiles));
-    const LaunchSet L =
-        capacity_set(w, size_t(p->max_fields), gs, gj, p->dtype, p->bn, p->zc);
+    const LaunchSet L = capacity_set(w, size_t(p->max_fields), gs, gj, p->dtype, p->bn, p->zc, p->with_order,
+                                     uint32_t(p->max_vertices));
     run_set(L, nullptr, nullptr, 0, w, s);
     return launch_status();
 }

@@ -68,6 +68,7 @@ struct FieldDesc {
     int32_t* desc;
     int32_t* ms;
     int32_t* info;     // {status, #minima, #maxima, K} or nullptr
+    int32_t* order;    // order field out (batches), or nullptr
     int32_t nx, ny, nz;
     uint32_t vbase;    // first launch-wide vertex id
     uint32_t sbase;    // first steepest tile (within its shape class)
@@ -97,6 +98,7 @@ __device__ __forceinline__ FieldDesc load_desc(const FieldDesc* table, uint32_t 
     d.desc = g->desc;
     d.ms = g->ms;
     d.info = g->info;
+    d.order = g->order;
     d.nx = g->nx;
     d.ny = g->ny;
     d.nz = g->nz;

@@ -454,7 +454,7 @@ __global__ __launch_bounds__(kBlock, sizeof(typename Src::key_t) == 4 ? 4 : 2) v
 // k_chunk_partition and k_invert_chunks write order[] one chunk at a time.  ihist/itotal: the per-worker id-range
 // counts and their totals (k_radix_hist with IDS, then the digit scan).
 template <class Src>
-__global__ __launch_bounds__(kBlock, 3) void k_rank_partition(Src src, uint32_t n, int shift,
+__global__ __launch_bounds__(kBlock, 3) void k_rank_partition(Src src, const uint32_t* count_ptr, uint32_t n, int shift,
                                                            const uint32_t* hist, const uint32_t* dtotal,
                                                            const uint32_t* ihist, const uint32_t* itotal,
                                                            int id_shift, uint64_t* out) {
@@ -470,7 +470,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_rank_partition(Src src, uint32_t 
     run[t] = block_exclusive_scan(dtotal[t], tmp, &tot) + hist[size_t(t) * gridDim.x + wk];
     irun[t] = block_exclusive_scan(itotal[t], tmp, &tot) + ihist[size_t(t) * gridDim.x + wk];
     uint32_t lo, hi;
-    worker_range(n, wk, gridDim.x, kTile, &lo, &hi);
+    worker_range(load_count(count_ptr, n), wk, gridDim.x, kTile, &lo, &hi);
     const uint64_t lt = lanemask_lt();
     // tiles are loaded as in k_radix_scatter: clamped indices, and the next
     // tile's loads issued before the current tile is written out
@@ -575,17 +575,21 @@ __device__ __forceinline__ uint32_t chunk_count(uint32_t c, uint32_t n) {
     return min(kChunk, n - base);
 }
 
-// chunk_fill: u32 per chunk, zero on entry.  Grid: one block per kTile pairs.
-__global__ __launch_bounds__(kBlock) void k_chunk_partition(const uint64_t* parts, uint32_t n, int range_shift,
+// chunk_fill: u32 per chunk, zero on entry.  Grid: one block per kTile pairs
+// (of the length count_ptr points to, when given, or n; blocks past it exit).
+__global__ __launch_bounds__(kBlock) void k_chunk_partition(const uint64_t* parts, const uint32_t* count_ptr,
+                                                            uint32_t n_host, int range_shift,
                                                             uint32_t* chunk_fill, uint64_t* out) {
     __shared__ uint32_t cnt[kMaxRel], start[kMaxRel], base[kMaxRel], fill[kMaxRel];
     __shared__ uint64_t stage[kTile];
     __shared__ uint32_t tmp[kWavesPerBlock];
     __shared__ uint32_t s_first;
     const int t = threadIdx.x;
+    const uint32_t n = load_count(count_ptr, n_host);
     // tiles numbered XCD by XCD, so that tiles reserving neighbouring runs
     // of a chunk mostly share an L2
     const uint32_t lo = xcd_worker() * uint32_t(kTile);
+    if (lo >= n) return;  // the whole block: no barrier has been passed yet
     const uint32_t hi = min(n, lo + uint32_t(kTile));
     for (int i = t; i < kMaxRel; i += kBlock) {
         cnt[i] = 0;

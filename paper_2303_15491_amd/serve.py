@@ -95,6 +95,7 @@ class Server:
         self.resident = 0
         self.next_plan = 0
         self.rejected = 0
+        self.batch_sizes = collections.Counter()  # fields per launched batch -> launches
         self.lock = threading.Lock()
 
     # -- submission --------------------------------------------------------------------
@@ -202,6 +203,7 @@ class Server:
             r.out = o
             r.t_launch = t
         self.inflight.append((pi, batch, ev))
+        self.batch_sizes[len(batch)] += 1
         self.next_plan = 1 - pi
         return True
 
@@ -239,7 +241,9 @@ class Server:
         return {"requests": len(self.done), "rejected": self.rejected, "vertices": verts,
                 "wall_s": t1 - t0, "throughput_mvps": verts / (t1 - t0) / 1e6,
                 "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-                "mean_ms": float(lat.mean() * 1e3), "max_ms": float(lat.max() * 1e3)}
+                "mean_ms": float(lat.mean() * 1e3), "max_ms": float(lat.max() * 1e3),
+                "batches": int(sum(self.batch_sizes.values())),
+                "batch_size_histogram": {int(k): int(v) for k, v in sorted(self.batch_sizes.items())}}
 
     def close(self):
         for p in self.plans:

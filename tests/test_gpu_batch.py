@@ -197,3 +197,91 @@ def test_full_uneven_batch_graph_against_oracle(torch):
         plan.close()
     finally:
         plmss.tune_set(**saved)
+
+
+def _check_with_order(f, o, label):
+    ref = oracle.segment(f)
+    info = o["info"].cpu().numpy()
+    assert info[0] == 0, label
+    for k in ("asc", "desc", "ms", "order"):
+        if k == "order" and o.get("order") is None:
+            continue
+        np.testing.assert_array_equal(o[k].cpu().numpy(), ref[k], err_msg=f"{label} {k}")
+    assert (info[1], info[2], info[3]) == (ref["n_min"], ref["n_max"], ref["K"]), label
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_batch_order_fields_match_oracle(torch, dtype):
+    """Order fields in a batch (Sec. "Preprocessing", per field): jobs with
+    and without an order array side by side, of every shape class, with ties
+    and special values in one field; each order field equals the oracle's."""
+    fs = [f.astype(dtype) for f in _mixed_fields(5)]
+    rng = np.random.default_rng(21)
+    fs[2] = rng.integers(0, 3, size=fs[2].shape).astype(dtype)  # heavy ties
+    fs[6] = np.array([np.inf], dtype)
+    dev = [torch.from_numpy(f).cuda() for f in fs]
+    outs = plmss._outs_for(dev, with_order=True)
+    for i in (1, 4, 9):
+        outs[i].pop("order")  # these jobs ask for no order field
+    _say(f"batch with order fields {np.dtype(dtype).name}")
+    plmss.segment_batch(dev, outs=outs)
+    torch.cuda.synchronize()
+    for i, (f, o) in enumerate(zip(fs, outs)):
+        _check_with_order(f, o, f"order batch field {i} {f.shape}")
+
+
+def test_batch_order_fields_many_fields(torch):
+    """More than 256 fields: the field index takes two digits of the sort."""
+    rng = np.random.default_rng(22)
+    fs = []
+    for i in range(300):
+        sh = [(3, 3), (2, 3, 4), (5,), (4, 4)][i % 4]
+        fs.append(rng.standard_normal(sh).astype(np.float32))
+    dev = [torch.from_numpy(f).cuda() for f in fs]
+    _say("batch of 300 fields with order")
+    outs = plmss.segment_batch(dev, with_order=True)
+    torch.cuda.synchronize()
+    for i, (f, o) in enumerate(zip(fs, outs)):
+        _check_with_order(f, o, f"many-field batch {i}")
+
+
+def test_batch_order_nan_stays_in_its_field(torch):
+    fs = _mixed_fields(6)
+    bad = fs[3].copy()
+    bad.ravel()[2] = np.nan
+    fs[3] = bad
+    _say("order batch with a NaN field")
+    outs = plmss.segment_batch([torch.from_numpy(f).cuda() for f in fs], with_order=True)
+    torch.cuda.synchronize()
+    for i, (f, o) in enumerate(zip(fs, outs)):
+        if i == 3:
+            assert int(o["info"][0]) == plmss.E_NAN
+        else:
+            _check_with_order(f, o, f"order batch field {i}")
+
+
+def test_plan_graph_with_order_fields(torch):
+    """A plan that builds order fields, replayed through its hipGraph for two
+    different batches in turn (A, B, A, B) with eager work in between."""
+    a = _mixed_fields(7)
+    b = [fields.smoothed_noise((30, 20, 10), 1.5, seed=19), fields.smoothed_noise((64, 64), 2.0, seed=20),
+         fields.smoothed_noise((7, 70, 9), 1.2, seed=21)]
+    da = [torch.from_numpy(f).cuda() for f in a]
+    db = [torch.from_numpy(f).cuda() for f in b]
+    need = [max(x, y) for x, y in zip(plmss.batch_needs(da), plmss.batch_needs(db))]
+    plan = plmss.Plan(need[0] + 5000, need[1] + 2, need[2] + 10, need[3] + 10, with_order=True)
+    for rnd, (fs, ds) in enumerate([(a, da), (b, db), (a, da), (b, db)]):
+        _say(f"order plan replay {rnd}")
+        outs = plan.set(ds)
+        plan.launch(graph=True)
+        torch.cuda.synchronize()
+        for i, (f, o) in enumerate(zip(fs, outs)):
+            _check_with_order(f, o, f"order replay {rnd} field {i}")
+        plmss.segment(da[0], with_order=True)
+        torch.cuda.synchronize()
+    plan.close()
+    plain = plmss.Plan(need[0], need[1], need[2], need[3])
+    with pytest.raises(plmss.PlmssError) as e:
+        plain.set(da, outs=plmss._outs_for(da, with_order=True))
+    assert e.value.code == plmss.E_ARG
+    plain.close()
