@@ -151,6 +151,34 @@ def test_float64_order_field_knobs(torch, knobs):
         plmss.tune_set(**saved)
 
 
+def _one_minimum_many_maxima(nx):
+    """Two rows: the lower rises to the right (its left end is the only
+    minimum), the upper alternates high and low (every high vertex is a
+    maximum), so one minimum pairs with nx / 2 maxima."""
+    x = np.arange(nx, dtype=np.float64)
+    return np.stack([1e-3 * x, 10.0 + (x % 2 == 0)]).astype(np.float32)
+
+
+@pytest.mark.parametrize("nx", [1500, 4096])
+def test_ms_ids_one_minimum_many_maxima(torch, nx):
+    """MS ids when one minimum pairs with thousands of maxima (one long run
+    of equal asc in the sorted pairs, spread over many chase tiles): the
+    same ids as the oracle, alone and inside a batch with ordinary fields."""
+    f = _one_minimum_many_maxima(nx)
+    ref, _ = _compare_full(torch, f, True, f"one minimum, {nx // 2} maxima")
+    assert ref["n_min"] == 1 and ref["n_max"] >= nx // 2
+    others = [fields.smoothed_noise((20, 30, 40), 1.5, seed=31), fields.smoothed_noise((64, 64), 2.0, seed=32)]
+    batch = [others[0], f, others[1]]
+    _say("batch with a large group")
+    outs = plmss.segment_batch([_dev(torch, a) for a in batch], with_order=True)
+    torch.cuda.synchronize()
+    for a, o in zip(batch, outs):
+        r = oracle.segment(a)
+        for k in ("asc", "desc", "ms", "order"):
+            np.testing.assert_array_equal(_host(o[k]), r[k], err_msg=f"large-group batch {a.shape} {k}")
+        assert int(o["info"][3]) == r["K"]
+
+
 def test_nan_reported_on_device(torch):
     f = fields.smoothed_noise((8, 9, 10), 1.5, 3)
     f[3, 4, 5] = np.nan
