@@ -375,7 +375,23 @@ def bench_marching(torch, plmss, lib, labels, steps: int, warmup: int, cpu_plane
     return res
 
 
-def bench_batched(torch, plmss, steps: int, warmup: int):
+def oracle_all_cores(host_fields):
+    """The oracle on every field, one call per field in a pool of host threads
+    (each call runs in C without the interpreter lock): the all-core CPU
+    figure for a set of independent fields.  Returns (seconds, threads)."""
+    import concurrent.futures
+
+    import oracle
+
+    threads = max(1, min(16, os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    with concurrent.futures.ThreadPoolExecutor(threads) as ex:
+        for _ in ex.map(oracle.segment, host_fields):
+            pass
+    return time.perf_counter() - t0, threads
+
+
+def bench_batched(torch, plmss, steps: int, warmup: int, cpu: bool = True):
     """The uneven batch (64 fields, sides 32..192): one plan launch (hipGraph)
     against a loop of plain per-field calls, timed two ways with the same
     synchronisation on both sides: launches only (one device synchronisation
@@ -473,6 +489,14 @@ def bench_batched(torch, plmss, steps: int, warmup: int):
     plan_o.close()
     del ws_o, outs_po, outs_bo
     torch.cuda.empty_cache()
+    cpu_all = None
+    if cpu:
+        log("oracle on every field of the batch, all host cores")
+        secs, threads = oracle_all_cores(host)
+        model, ncpu = cpu_info()
+        cpu_all = {"value": nv / secs / 1e6, "unit": "Mvertices/s", "cores": threads, "kind": "oracle",
+                   "sample": f"all 64 fields, one serial oracle call per field on {threads} host threads, "
+                             f"{secs:.2f} s", "host_cpu": model, "host_nproc": ncpu}
     return {"workload": "64 fields, sides uniform in 32..192, sum of 16..256 Gaussians + N(0,0.02) (seeds 4+j)",
             "vertices": nv, "batched_ms": t_batch, "plain_loop_ms": t_plain,
             "batched_mvps": nv / t_batch / 1e3, "plain_loop_mvps": nv / t_plain / 1e3,
@@ -485,10 +509,10 @@ def bench_batched(torch, plmss, steps: int, warmup: int):
                                   "batched_mvps": nv / t_batch_o / 1e3, "plain_loop_mvps": nv / t_plain_o / 1e3,
                                   "speedup": t_plain_o / t_batch_o, "identical": bool(same_o),
                                   "timing": "launches only, as above; every field's order field built"},
-            "identical": bool(same), "tuned": tuned}
+            "cpu_all_cores": cpu_all, "identical": bool(same), "tuned": tuned}
 
 
-def bench_serving(torch, plmss, n_requests: int, rate: float, saturate_rate: float):
+def bench_serving(torch, plmss, n_requests: int, rate: float, saturate_rate: float, cpu: bool = True):
     """Poisson arrivals of mixed 2-D (128^2..2048^2) and 3-D (64^3..384^3)
     requests through the continuous-batching server, in real time: at the
     workload's rate, and at a rate far above what the GPU sustains (its
@@ -552,6 +576,15 @@ def bench_serving(torch, plmss, n_requests: int, rate: float, saturate_rate: flo
                          "timing": "upload from page-locked memory, plmss_segment, device synchronisation, per "
                                    "request, back to back (no arrival gaps)"}
     res["saturated_vs_plain_loop"] = res["saturated"]["throughput_mvps"] / res["plain_loop"]["throughput_mvps"]
+    if cpu:
+        log("oracle on the serving pool's fields, all host cores")
+        secs, threads = oracle_all_cores(pool_np)
+        model, ncpu = cpu_info()
+        pv = sum(int(f.size) for f in pool_np)
+        res["cpu_all_cores"] = {"value": pv / secs / 1e6, "unit": "Mvertices/s", "cores": threads, "kind": "oracle",
+                                "sample": f"the 64 distinct request fields of the mix ({pv} vertices), one serial "
+                                          f"oracle call per field on {threads} host threads, {secs:.2f} s",
+                                "host_cpu": model, "host_nproc": ncpu}
     res["workload"] = ("Poisson arrivals; half 2-D n^2 (n in 128..2048), half 3-D n^3 (n in 64..384), smoothed "
                        "N(0,1) noise, sigma 1.5..4 (seed 5)")
     del ws, devbuf, outs
@@ -750,9 +783,10 @@ def main():
                                                    cpu_planes=0)
         del t2, seg
         torch.cuda.empty_cache()
-    batched = None if args.no_batched else bench_batched(torch, plmss, steps=max(3, args.steps // 2), warmup=2)
-    serving = (bench_serving(torch, plmss, args.serve_requests, args.serve_rate, args.serve_saturate_rate)
-               if args.serve_requests else None)
+    batched = (None if args.no_batched else
+               bench_batched(torch, plmss, steps=max(3, args.steps // 2), warmup=2, cpu=args.cpu_slab > 0))
+    serving = (bench_serving(torch, plmss, args.serve_requests, args.serve_rate, args.serve_saturate_rate,
+                             cpu=args.cpu_slab > 0) if args.serve_requests else None)
     out = {
         "metric": METRIC, "value": value, "unit": "Mvertices/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
