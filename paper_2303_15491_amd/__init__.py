@@ -219,8 +219,10 @@ def segment(field, with_order: bool = False, workspace=None, stream=None, out=No
         out["info"] = torch.empty(4, dtype=torch.int32, device=dev)
     lib = library()
     ws = _workspace(lib.plmss_workspace_bytes(dims, code, int(with_order)), dev, workspace)
+    if with_order and out.get("order") is None:
+        raise ValueError("with_order needs an order tensor in out")
     job = Job(field.data_ptr(), dims, code, out["asc"].data_ptr(), out["desc"].data_ptr(),
-              out["ms"].data_ptr(), out["order"].data_ptr() if out.get("order") is not None else None,
+              out["ms"].data_ptr(), out["order"].data_ptr() if with_order else None,
               out["info"].data_ptr())
     _check(lib.plmss_segment(ctypes.byref(job), _ptr(ws), ws.numel(), _stream(stream)), "plmss_segment")
     return out
@@ -243,8 +245,10 @@ def segment_static(field, with_order: bool = False, stream=None, out=None):
     code = _field_check(field)
     if out is None:
         out = _segment_outs(field, with_order)
+    if with_order and out.get("order") is None:
+        raise ValueError("with_order needs an order tensor in out")
     job = Job(field.data_ptr(), dims_of(field.shape), code, out["asc"].data_ptr(), out["desc"].data_ptr(),
-              out["ms"].data_ptr(), out["order"].data_ptr() if out.get("order") is not None else None,
+              out["ms"].data_ptr(), out["order"].data_ptr() if with_order else None,
               out["info"].data_ptr())
     _check(library().plmss_segment_static(ctypes.byref(job), _stream(stream)), "plmss_segment_static")
     return out
