@@ -708,7 +708,7 @@ __device__ __forceinline__ void jtile_xyz(const FieldDesc& fd, uint32_t lt, int 
 // CHASE: labels from the tile-compressed pointers U/D (written back as they
 // are followed).  Otherwise the labels are read from the field's desc/asc.
 template <class T, bool CHASE>
-__global__ __launch_bounds__(kChaseBlock) void k_chase(Fields F, uint32_t* U, uint32_t* D, int bn,
+__global__ __launch_bounds__(kChaseBlock, 6) void k_chase(Fields F, uint32_t* U, uint32_t* D, int bn,
                                                   uint64_t* rec_keys, uint32_t* rec_vals, uint32_t* rec_count) {
     __shared__ uint64_t table[kHash];
     __shared__ uint16_t dense[kHash];
@@ -792,26 +792,37 @@ __global__ __launch_bounds__(kChaseBlock) void k_chase(Fields F, uint32_t* U, ui
             if (pending && fd.info) gmem(fd.info)[0] = -7;  // PLMSS_E_NOCONV
         }
         __syncthreads();
-        // insert every vertex's pair; slot[i] = its hash slot
+        // insert every vertex's pair; slot[i] = its hash slot.  Neighbouring
+        // lanes mostly hold the same pair (MS regions span several vertices
+        // of a row): only the first lane of each run of equal pairs inserts,
+        // the others take its slot by a shuffle.
+        const uint64_t upto_me = lanemask_lt() | (uint64_t(1) << lane);
         uint32_t slot[kChasePer];
 #pragma unroll
         for (int i = 0; i < kChasePer; ++i) {
-            slot[i] = 0;
-            if (!ok[i]) continue;
-            const uint64_t key = (uint64_t(pd[i]) << bn) | uint64_t(pu[i]);
-            uint32_t h = pair_hash(key) & (kHash - 1);
-            for (;;) {
-                uint64_t cur = table[h];
-                if (cur == kEmpty) {
-                    cur = atomicCAS(reinterpret_cast<unsigned long long*>(&table[h]),
-                                    static_cast<unsigned long long>(kEmpty),
-                                    static_cast<unsigned long long>(key));
-                    if (cur == kEmpty) cur = key;
+            const uint64_t key = ok[i] ? (uint64_t(pd[i]) << bn) | uint64_t(pu[i]) : kEmpty;
+            const uint32_t klo = uint32_t(key), khi = uint32_t(key >> 32);
+            const uint32_t llo = uint32_t(__shfl_up(int(klo), 1)), lhi = uint32_t(__shfl_up(int(khi), 1));
+            const bool first = lane == 0 || klo != llo || khi != lhi;
+            uint32_t h = 0;
+            if (ok[i] && first) {
+                h = pair_hash(key) & (kHash - 1);
+                for (;;) {
+                    uint64_t cur = table[h];
+                    if (cur == kEmpty) {
+                        cur = atomicCAS(reinterpret_cast<unsigned long long*>(&table[h]),
+                                        static_cast<unsigned long long>(kEmpty),
+                                        static_cast<unsigned long long>(key));
+                        if (cur == kEmpty) cur = key;
+                    }
+                    if (cur == key) break;
+                    h = (h + 1) & (kHash - 1);
                 }
-                if (cur == key) break;
-                h = (h + 1) & (kHash - 1);
             }
-            slot[i] = h;
+            // the run's first lane: the highest lane at or below this one
+            // that starts a run (its pair is this lane's)
+            const uint64_t starts = __ballot(first);
+            slot[i] = uint32_t(__shfl(int(h), top_lane(starts & upto_me)));
         }
         __syncthreads();
         // number the occupied slots: wave w scans slots [w*kHash/8, (w+1)*kHash/8)
