@@ -341,13 +341,28 @@ def bench_marching(torch, plmss, lib, labels, steps: int, warmup: int, cpu_plane
         _, launches = timed_region(gstep, gsteps, torch, lib, trace, 4 * gsteps)
         lib.plmss_trace_destroy(trace)
         avg = per_kernel(launches, gsteps)["march_geometry"]["avg_launch_ms"]
+        # the same output buffers written by a plain fill, in the same run: the
+        # write rate this machine gives buffers of this size
+        fills = []
+        for _ in range(3):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            xyz.fill_(1.0)
+            sides.fill_(1)
+            b.record()
+            b.synchronize()
+            fills.append(a.elapsed_time(b))
+        fill_ms = sorted(fills)[1]
         per_prim = 4 * pts[0] * pts[1] + 8
         nbytes = 4.0 * labels.numel() + 8.0 * (rows + 1) + per_prim * total
         res[key] = {"primitives": total, "ms_per_call": wall / gsteps, "kernel_avg_launch_ms": avg,
                     "output_gb": per_prim * total / 1e9, "algorithmic_bytes_per_launch": nbytes,
                     "basis": f"4 B/vertex labels read + {per_prim} B/primitive written (points, side labels)",
                     "achieved_gbs": nbytes / (avg * 1e-3) / 1e9, "frac": nbytes / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                    "primitives_per_s": total / (avg * 1e-3)}
+                    "primitives_per_s": total / (avg * 1e-3),
+                    "write_only_fill_ms": fill_ms,
+                    "write_only_fill_gbs": (xyz.numel() + sides.numel()) * 4 / (fill_ms * 1e-3) / 1e9,
+                    "kernel_vs_fill": fill_ms / avg}
         del xyz, sides
         torch.cuda.empty_cache()
     if cpu_planes > 0:
