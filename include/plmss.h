@@ -59,6 +59,7 @@ extern "C" {
 #define PLMSS_E_WORKSPACE (-5) /* workspace NULL or smaller than required */
 #define PLMSS_E_HIP (-6)       /* a HIP launch or runtime call failed */
 #define PLMSS_E_NOCONV (-7)    /* path compression hit its iteration cap (device-side) */
+#define PLMSS_E_INTERNAL (-8)  /* an internal invariant failed (device-side; the order field is wrong) */
 
 /* Field element types. */
 #define PLMSS_F32 0

@@ -21,7 +21,7 @@ __all__ = ["PlmssError", "library", "segment", "segment_static", "STATIC_MAX_VER
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libplmss.so")
 
-OK, E_ARG, E_DIMS, E_TOO_LARGE, E_NAN, E_WORKSPACE, E_HIP = 0, -1, -2, -3, -4, -5, -6
+OK, E_ARG, E_DIMS, E_TOO_LARGE, E_NAN, E_WORKSPACE, E_HIP, E_NOCONV, E_INTERNAL = 0, -1, -2, -3, -4, -5, -6, -7, -8
 F32, F64 = 0, 1
 MARCH_SEPARATORS, MARCH_BOUNDARIES = 0, 1
 STATIC_MAX_VERTICES = 1 << 21  # PLMSS_STATIC_MAX_VERTICES

@@ -91,10 +91,17 @@ struct PackedFieldDst {
 // (launch-wide id g, position p) becomes order_j[g - vbase_j] = p - vbase_j in
 // the order array of the field j holding g (fields without one are skipped).
 // Grid: one block per chunk of the length count_ptr points to (or n).
+// A pair lost by the regrouping (*bad) is reported in every field's info[0]
+// as PLMSS_E_INTERNAL.
 __global__ __launch_bounds__(kInvertBlock) void k_invert_chunks_batch(const uint64_t* parts,
                                                                       const uint32_t* count_ptr, uint32_t n_host,
-                                                                      Fields F) {
+                                                                      Fields F, const uint32_t* bad) {
     __shared__ uint32_t buf[kChunk];
+    if (blockIdx.x == 0 && *bad)
+        for (uint32_t f = threadIdx.x; f < fields_count(F); f += kInvertBlock) {
+            int32_t* info = gmem(F.table)[f].info;
+            if (info) gmem(info)[0] = -8;  // PLMSS_E_INTERNAL
+        }
     const uint32_t n = load_count(count_ptr, n_host);
     const uint32_t base = blockIdx.x << kChunkBits;
     if (base >= n) return;

@@ -118,8 +118,8 @@ struct Sizes {
 };
 
 // Order-sort bookkeeping: totals of the id ranges, then one fill counter per
-// id chunk (at most 2^31 / kChunk).
-constexpr size_t kSortAux = kRadix + (size_t(1) << (31 - kChunkBits));
+// id chunk (at most 2^31 / kChunk), then the regrouping's lost-pair flag.
+constexpr size_t kSortAux = kRadix + (size_t(1) << (31 - kChunkBits)) + 1;
 
 constexpr uint64_t n_tiles(uint64_t n) { return (n + kTile - 1) / kTile; }
 
@@ -328,18 +328,19 @@ void invert_by_chunks(Src src, const uint32_t* cnt, uint32_t n, unsigned workers
         k_rank_partition<Src><<<workers, kBlock, 0, s>>>(src, cnt, n, last, w.hist, w.dtotal, ihist, itotal,
                                                          id_shift, parts);
     });
+    uint32_t* bad = chunk_fill + chunks;  // set if the regrouping lost a pair
     launch(PLMSS_KERNEL_MISC, s, [&] {
-        k_zero_u32<<<std::min(256u, (chunks + kBlock - 1) / kBlock), kBlock, 0, s>>>(chunk_fill, chunks);
+        k_zero_u32<<<std::min(256u, (chunks + 1 + kBlock - 1) / kBlock), kBlock, 0, s>>>(chunk_fill, chunks + 1);
     });
     launch(PLMSS_KERNEL_ORDER_REGROUP, s, [&] {
-        k_chunk_partition<<<tiles, kBlock, 0, s>>>(parts, cnt, n, id_shift, chunk_fill, parts2);
+        k_chunk_partition<<<tiles, kBlock, 0, s>>>(parts, cnt, n, id_shift, chunk_fill, parts2, bad);
     });
     if (batch)
         launch(PLMSS_KERNEL_ORDER_INVERT, s,
-               [&] { k_invert_chunks_batch<<<chunks, kInvertBlock, 0, s>>>(parts2, cnt, n, *batch); });
+               [&] { k_invert_chunks_batch<<<chunks, kInvertBlock, 0, s>>>(parts2, cnt, n, *batch, bad); });
     else
         launch(PLMSS_KERNEL_ORDER_INVERT, s,
-               [&] { k_invert_chunks<<<chunks, kInvertBlock, 0, s>>>(parts2, n, order); });
+               [&] { k_invert_chunks<<<chunks, kInvertBlock, 0, s>>>(parts2, n, order, bad, info); });
 }
 
 // The passes of an order sort after its first: middle passes at shifts
@@ -998,6 +999,7 @@ const char* plmss_status_string(int code) {
         case PLMSS_E_WORKSPACE: return "workspace missing, misaligned or too small";
         case PLMSS_E_HIP: return "HIP runtime or launch error";
         case PLMSS_E_NOCONV: return "path compression did not converge (pointers do not form a forest)";
+        case PLMSS_E_INTERNAL: return "internal error: the order field's inversion lost a pair";
         default: return "unknown status";
     }
 }

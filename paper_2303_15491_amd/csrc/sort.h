@@ -577,9 +577,13 @@ __device__ __forceinline__ uint32_t chunk_count(uint32_t c, uint32_t n) {
 
 // chunk_fill: u32 per chunk, zero on entry.  Grid: one block per kTile pairs
 // (of the length count_ptr points to, when given, or n; blocks past it exit).
+// Every pair has a place by construction (the ids are a permutation, ranges
+// other than the last hold at least kTile ids); a pair that found none all
+// the same sets *bad, which the inversion reports instead of a silently
+// wrong order field.
 __global__ __launch_bounds__(kBlock) void k_chunk_partition(const uint64_t* parts, const uint32_t* count_ptr,
                                                             uint32_t n_host, int range_shift,
-                                                            uint32_t* chunk_fill, uint64_t* out) {
+                                                            uint32_t* chunk_fill, uint64_t* out, uint32_t* bad) {
     __shared__ uint32_t cnt[kMaxRel], start[kMaxRel], base[kMaxRel], fill[kMaxRel];
     __shared__ uint64_t stage[kTile];
     __shared__ uint32_t tmp[kWavesPerBlock];
@@ -603,11 +607,15 @@ __global__ __launch_bounds__(kBlock) void k_chunk_partition(const uint64_t* part
     uint32_t rel[kItems];
 #pragma unroll
     for (int i = 0; i < kItems; ++i) x[i] = parts[min(lo + uint32_t(i) * kBlock + t, hi - 1u)];
+    bool lost = false;
 #pragma unroll
     for (int i = 0; i < kItems; ++i) {
         const uint32_t j = lo + uint32_t(i) * kBlock + t;
         rel[i] = j < hi ? (uint32_t(x[i] >> 32) >> kChunkBits) - first : uint32_t(kMaxRel);
-        if (rel[i] < uint32_t(kMaxRel)) atomicAdd(&cnt[rel[i]], 1u);
+        if (rel[i] < uint32_t(kMaxRel))
+            atomicAdd(&cnt[rel[i]], 1u);
+        else if (j < hi)
+            lost = true;
     }
     __syncthreads();
     constexpr int kPer = kMaxRel / kBlock;
@@ -639,13 +647,21 @@ __global__ __launch_bounds__(kBlock) void k_chunk_partition(const uint64_t* part
             const uint32_t ch = uint32_t(y >> 32) >> kChunkBits;
             const uint32_t r = ch - first;
             const uint32_t slot = base[r] + (j - start[r]);
-            if (slot < chunk_count(ch, n)) out[(size_t(ch) << kChunkBits) + slot] = y;
+            if (slot < chunk_count(ch, n))
+                out[(size_t(ch) << kChunkBits) + slot] = y;
+            else
+                lost = true;
         }
     }
+    if (lost) atomicOr(bad, 1u);
 }
 
 // One block per chunk: order[c*kChunk + i] for the chunk's pairs, through LDS.
-__global__ __launch_bounds__(kInvertBlock) void k_invert_chunks(const uint64_t* parts, uint32_t n, int32_t* order) {
+// A pair lost by the regrouping (*bad) is reported in info[0] (nullable) as
+// PLMSS_E_INTERNAL.
+__global__ __launch_bounds__(kInvertBlock) void k_invert_chunks(const uint64_t* parts, uint32_t n, int32_t* order,
+                                                                const uint32_t* bad, int32_t* info) {
+    if (blockIdx.x == 0 && threadIdx.x == 0 && info && *bad) info[0] = -8;  // PLMSS_E_INTERNAL
     __shared__ uint32_t buf[kChunk];
     const uint32_t base = blockIdx.x << kChunkBits;
     const uint32_t cnt = chunk_count(blockIdx.x, n);

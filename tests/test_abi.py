@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings():
     lib = plmss.library()
-    for code in (0, -1, -2, -3, -4, -5, -6, -7):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8):
         s = lib.plmss_status_string(code).decode()
         assert s and s != "unknown status"
     assert lib.plmss_status_string(42).decode() == "unknown status"

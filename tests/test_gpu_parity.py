@@ -179,6 +179,25 @@ def test_ms_ids_one_minimum_many_maxima(torch, nx):
         assert int(o["info"][3]) == r["K"]
 
 
+# Lengths at the edges of the order field's inversion: one id chunk (2^15),
+# id ranges of 2^15 .. 2^23 ids (their size follows the length), tiles of
+# the regrouping that straddle two ranges, and a last range shorter than a tile.
+@pytest.mark.parametrize("n", [4095, 4096, 32767, 32768, 32769, 65537, 2 ** 21 + 4097, 2 ** 22 - 1, 2 ** 22,
+                               2 ** 22 + 1, 2 ** 23 + 3000])
+def test_order_field_at_range_and_chunk_edges(torch, n):
+    """The order field of a line of n random values (every order equally
+    likely, ties included): equal to the oracle's, and no lost pair reported."""
+    rng = np.random.default_rng(n)
+    f = rng.standard_normal(n).astype(np.float32)
+    f[rng.random(n) < 0.001] = 0.5  # a few ties
+    _say(f"order field n={n}")
+    order, info = plmss.order_field(_dev(torch, f))
+    torch.cuda.synchronize()
+    assert int(info[0]) == 0
+    ref, _ = oracle.order_field(f)
+    np.testing.assert_array_equal(_host(order), ref)
+
+
 def test_nan_reported_on_device(torch):
     f = fields.smoothed_noise((8, 9, 10), 1.5, 3)
     f[3, 4, 5] = np.nan
