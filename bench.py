@@ -752,6 +752,17 @@ def main():
                 "kernel_source_digest": kernel_source_digest(),
                 "copy_probe_gbs": copy_gbs,
                 "copy_probe": "device-to-device copy of 1 GiB (read + write bytes / time), median of 5"}
+    # the next kinds by time per step, each against its own algorithmic bytes
+    # (at 512^3 the chase and the two middle radix scatters are within a few
+    # percent of each other, so either can come out on top)
+    top = []
+    for k in sorted(kern, key=lambda k: -kern[k]["ms_per_step"])[:4]:
+        b = algo_bytes(k, knobs["order_invert"])
+        a = b * n / (kern[k]["avg_launch_ms"] * 1e-3) / 1e9 if b else None
+        top.append({"kind": k, "symbol": HEADLINE_SYMBOLS.get(k), "ms_per_step": kern[k]["ms_per_step"],
+                    "avg_launch_ms": kern[k]["avg_launch_ms"], "algorithmic_bytes_per_vertex": b,
+                    "frac": a / HBM_PEAK_GBS if a else None})
+    roofline["top_kinds"] = top
 
     # CPU baseline: the oracle on a bounded slab of the same field, one core
     cpu = None
