@@ -30,6 +30,18 @@ __device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
     return (__attribute__((address_space(1))) T*)p;
 }
 
+// Element i of a global array.  With O32 the address is the array's base plus
+// a 32-bit byte offset (valid while i * sizeof(T) < 2^32): the base stays in
+// scalar registers and each address costs one vector register, not a pair.
+template <bool O32, typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gelem(T* base, uint32_t i) {
+    if constexpr (O32)
+        return (__attribute__((address_space(1))) T*)((__attribute__((address_space(1))) char*)base +
+                                                       i * uint32_t(sizeof(T)));
+    else
+        return gmem(base) + i;
+}
+
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 __device__ __forceinline__ int wave_id() { return threadIdx.x / kWave; }
 

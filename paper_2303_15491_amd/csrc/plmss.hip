@@ -579,13 +579,21 @@ void launch_chase_cls(int c, const Fields& F, unsigned grid, uint32_t* U, uint32
                       hipStream_t s) {
     if (grid == 0) return;
     uint64_t* rec = reinterpret_cast<uint64_t*>(w.keys[1]);
+    // ids below 2^30: 32-bit byte offsets address every array of the chase
+    const bool o32 = bn <= 30;
     launch(PLMSS_KERNEL_JUMP, s, [&] {
-        if (c == 0)
-            k_chase<JTile3, CHASE><<<grid, kChaseBlock, 0, s>>>(F, U, D, bn, rec, w.vals[0], w.counters + 0);
+        if (c == 0 && o32)
+            k_chase<JTile3, CHASE, true><<<grid, kChaseBlock, 0, s>>>(F, U, D, bn, rec, w.vals[0], w.counters + 0);
+        else if (c == 0)
+            k_chase<JTile3, CHASE, false><<<grid, kChaseBlock, 0, s>>>(F, U, D, bn, rec, w.vals[0], w.counters + 0);
+        else if (c == 1 && o32)
+            k_chase<JTile2, CHASE, true><<<grid, kChaseBlock, 0, s>>>(F, U, D, bn, rec, w.vals[0], w.counters + 0);
         else if (c == 1)
-            k_chase<JTile2, CHASE><<<grid, kChaseBlock, 0, s>>>(F, U, D, bn, rec, w.vals[0], w.counters + 0);
+            k_chase<JTile2, CHASE, false><<<grid, kChaseBlock, 0, s>>>(F, U, D, bn, rec, w.vals[0], w.counters + 0);
+        else if (o32)
+            k_chase<JTile1, CHASE, true><<<grid, kChaseBlock, 0, s>>>(F, U, D, bn, rec, w.vals[0], w.counters + 0);
         else
-            k_chase<JTile1, CHASE><<<grid, kChaseBlock, 0, s>>>(F, U, D, bn, rec, w.vals[0], w.counters + 0);
+            k_chase<JTile1, CHASE, false><<<grid, kChaseBlock, 0, s>>>(F, U, D, bn, rec, w.vals[0], w.counters + 0);
     });
 }
 

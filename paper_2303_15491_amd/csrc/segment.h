@@ -677,6 +677,14 @@ template <int JX, int JY, int JZ>
 struct JTile {
     static_assert(JX * JY * JZ == kJV, "tile size");
     static constexpr int X = JX, Y = JY, Z = JZ;
+    // a thread's vertices are kChaseBlock entries apart in the tile: the
+    // step between them in x, y, z (the same for every thread)
+    static constexpr int SX = kChaseBlock % JX;
+    static constexpr int SY = (kChaseBlock / JX) % JY;
+    static constexpr int SZ = kChaseBlock / (JX * JY);
+    static_assert(SX * 1 + SY * JX + SZ * JX * JY == kChaseBlock && (SX == 0 || JX % kChaseBlock == 0) &&
+                      (SY == 0 || (JY % SY == 0 && JX * SY == kChaseBlock)),
+                  "a thread's vertices differ in one coordinate");
 };
 using JTile3 = JTile<32, 8, 8>;
 using JTile2 = JTile<64, 32, 1>;
@@ -707,18 +715,26 @@ __device__ __forceinline__ void jtile_xyz(const FieldDesc& fd, uint32_t lt, int 
 
 // CHASE: labels from the tile-compressed pointers U/D (written back as they
 // are followed).  Otherwise the labels are read from the field's desc/asc.
-template <class T, bool CHASE>
-__global__ __launch_bounds__(kChaseBlock, 6) void k_chase(Fields F, uint32_t* U, uint32_t* D, int bn,
+// O32: every vertex id of the launch is below 2^30, so U, D and the label
+// arrays are addressed by 32-bit byte offsets.
+template <class T, bool CHASE, bool O32>
+__global__ __launch_bounds__(kChaseBlock, 8) void k_chase(Fields F, uint32_t* U, uint32_t* D, int bn,
                                                   uint64_t* rec_keys, uint32_t* rec_vals, uint32_t* rec_count) {
     __shared__ uint64_t table[kHash];
     __shared__ uint16_t dense[kHash];
     __shared__ uint32_t tmp[kChaseWaves];
     __shared__ uint32_t s_base;
-    const int t = threadIdx.x, lane = lane_id(), w = wave_id();
     uint32_t tfirst, tlast;
     block_tiles(F.dev_tiles ? gmem(F.dev_tiles)[1] : F.j_tiles, &tfirst, &tlast);
     FieldCursor<false> cursor(F);
     for (uint32_t tile = tfirst; tile < tlast; ++tile) {
+        // the thread index is made opaque to the compiler once per tile, so
+        // that what derives from it (lane masks, in-tile coordinates) is
+        // recomputed in each tile rather than held in registers across tiles
+        // (with it, the kernel fits 64 registers: eight waves per SIMD)
+        uint32_t tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        const int t = int(tid), lane = t & (kWave - 1), w = t / kWave;
         const FieldDesc fd = cursor.at(F, tile);
         const uint32_t lt = tile - fd.jbase;
         __syncthreads();  // the previous tile's readers of LDS are done
@@ -726,20 +742,25 @@ __global__ __launch_bounds__(kChaseBlock, 6) void k_chase(Fields F, uint32_t* U,
         for (int i = 0; i < kHash / kChaseBlock; ++i) table[t + i * kChaseBlock] = kEmpty;
         uint32_t lv[kChasePer], pu[kChasePer], pd[kChasePer];
         bool ok[kChasePer];
+        // the thread's vertices: the first one's coordinates, then a fixed
+        // step (in one coordinate) to each of the others
+        int x0, y0, z0;
+        jtile_xyz<T>(fd, lt, t, &x0, &y0, &z0);
+        const uint32_t v0 = (uint32_t(z0) * uint32_t(fd.ny) + uint32_t(y0)) * uint32_t(fd.nx) + uint32_t(x0);
+        const uint32_t vstep = uint32_t(T::SX) + uint32_t(T::SY) * uint32_t(fd.nx) +
+                               uint32_t(T::SZ) * uint32_t(fd.nx) * uint32_t(fd.ny);
 #pragma unroll
         for (int i = 0; i < kChasePer; ++i) {
-            int x, y, z;
-            jtile_xyz<T>(fd, lt, t + i * kChaseBlock, &x, &y, &z);
-            ok[i] = x < fd.nx && y < fd.ny && z < fd.nz;
-            lv[i] = ok[i] ? (uint32_t(z) * uint32_t(fd.ny) + uint32_t(y)) * uint32_t(fd.nx) + uint32_t(x) : 0u;
+            ok[i] = x0 + i * T::SX < fd.nx && y0 + i * T::SY < fd.ny && z0 + i * T::SZ < fd.nz;
+            lv[i] = ok[i] ? v0 + uint32_t(i) * vstep : 0u;
             // lanes past the field's edge read its vertex 0 (lv = 0) and drop
             // the value, so the loads need no branch and issue together
             if (CHASE) {
-                pu[i] = gmem(U)[fd.vbase + lv[i]];
-                pd[i] = gmem(D)[fd.vbase + lv[i]];
+                pu[i] = *gelem<O32>(U, fd.vbase + lv[i]);
+                pd[i] = *gelem<O32>(D, fd.vbase + lv[i]);
             } else {
-                pu[i] = uint32_t(gmem(fd.desc)[lv[i]]) + fd.vbase;
-                pd[i] = uint32_t(gmem(fd.asc)[lv[i]]) + fd.vbase;
+                pu[i] = uint32_t(*gelem<O32>(fd.desc, lv[i])) + fd.vbase;
+                pd[i] = uint32_t(*gelem<O32>(fd.asc, lv[i])) + fd.vbase;
             }
         }
 #pragma unroll
@@ -761,18 +782,18 @@ __global__ __launch_bounds__(kChaseBlock, 6) void k_chase(Fields F, uint32_t* U,
                 for (int i = 0; i < kChasePer; ++i) {
                     nu[i] = pu[i];
                     nd[i] = pd[i];
-                    if (!(pu[i] & kMark)) nu[i] = gmem(U)[pu[i]];
-                    if (!(pd[i] & kMark)) nd[i] = gmem(D)[pd[i]];
+                    if (!(pu[i] & kMark)) nu[i] = *gelem<O32>(U, pu[i]);
+                    if (!(pd[i] & kMark)) nd[i] = *gelem<O32>(D, pd[i]);
                 }
                 pending = false;
 #pragma unroll
                 for (int i = 0; i < kChasePer; ++i) {
                     if (!(pu[i] & kMark)) {
-                        if (hops) gmem(U)[fd.vbase + lv[i]] = nu[i];
+                        if (hops) *gelem<O32>(U, fd.vbase + lv[i]) = nu[i];
                         pending = true;
                     }
                     if (!(pd[i] & kMark)) {
-                        if (hops) gmem(D)[fd.vbase + lv[i]] = nd[i];
+                        if (hops) *gelem<O32>(D, fd.vbase + lv[i]) = nd[i];
                         pending = true;
                     }
                     pu[i] = nu[i];
@@ -785,8 +806,8 @@ __global__ __launch_bounds__(kChaseBlock, 6) void k_chase(Fields F, uint32_t* U,
                 pu[i] &= ~kMark;
                 pd[i] &= ~kMark;
                 if (ok[i]) {
-                    gmem(fd.desc)[lv[i]] = int32_t(pu[i] - fd.vbase);
-                    gmem(fd.asc)[lv[i]] = int32_t(pd[i] - fd.vbase);
+                    *gelem<O32>(fd.desc, lv[i]) = int32_t(pu[i] - fd.vbase);
+                    *gelem<O32>(fd.asc, lv[i]) = int32_t(pd[i] - fd.vbase);
                 }
             }
             if (pending && fd.info) gmem(fd.info)[0] = -7;  // PLMSS_E_NOCONV
@@ -796,7 +817,7 @@ __global__ __launch_bounds__(kChaseBlock, 6) void k_chase(Fields F, uint32_t* U,
         // lanes mostly hold the same pair (MS regions span several vertices
         // of a row): only the first lane of each run of equal pairs inserts,
         // the others take its slot by a shuffle.
-        const uint64_t upto_me = lanemask_lt() | (uint64_t(1) << lane);
+        const uint64_t upto_me = ~0ull >> (kWave - 1 - lane);
         uint32_t slot[kChasePer];
 #pragma unroll
         for (int i = 0; i < kChasePer; ++i) {
@@ -828,7 +849,6 @@ __global__ __launch_bounds__(kChaseBlock, 6) void k_chase(Fields F, uint32_t* U,
         // number the occupied slots: wave w scans slots [w*kHash/8, (w+1)*kHash/8)
         // row by row (64 consecutive slots per row), so LDS reads are conflict-free
         constexpr int kRows = kHash / kChaseBlock;
-        const uint64_t lt_mask = lanemask_lt();
         uint32_t wcount = 0;
 #pragma unroll
         for (int i = 0; i < kRows; ++i)
@@ -850,7 +870,9 @@ __global__ __launch_bounds__(kChaseBlock, 6) void k_chase(Fields F, uint32_t* U,
             const uint64_t k = table[sl];
             const uint64_t occ = __ballot(k != kEmpty);
             if (k != kEmpty) {
-                const uint32_t jj = j + uint32_t(__popcll(occ & lt_mask));
+                // occupied slots below this lane
+                const uint32_t jj =
+                    j + __builtin_amdgcn_mbcnt_hi(uint32_t(occ >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(occ), 0u));
                 dense[sl] = uint16_t(jj);
                 rec_keys[base + jj] = k;
                 rec_vals[base + jj] = base + jj;
@@ -860,7 +882,7 @@ __global__ __launch_bounds__(kChaseBlock, 6) void k_chase(Fields F, uint32_t* U,
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < kChasePer; ++i)
-            if (ok[i]) gmem(fd.ms)[lv[i]] = int32_t(base + dense[slot[i]]);
+            if (ok[i]) *gelem<O32>(fd.ms, lv[i]) = int32_t(base + dense[slot[i]]);
     }
 }
 
