@@ -82,11 +82,16 @@ __device__ __forceinline__ bool is_nan(double f) {
 // block sum.  Must be called by all threads of the block.
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* tmp,
                                                          uint32_t* total) {
-    const int lane = lane_id(), w = wave_id();
+    // the thread index is opaque to the compiler here, so that the shuffle
+    // addresses derived from it are recomputed at each call instead of being
+    // held in registers (or spilled) across a kernel's loop
+    uint32_t tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int lane = int(tid) & (kWave - 1), w = int(tid) / kWave;
     uint32_t inc = x;
 #pragma unroll
     for (int d = 1; d < kWave; d <<= 1) {
-        uint32_t y = __shfl_up(inc, d, kWave);
+        const uint32_t y = uint32_t(__builtin_amdgcn_ds_bpermute((lane - d) << 2, int(inc)));
         if (lane >= d) inc += y;
     }
     if (lane == kWave - 1) tmp[w] = inc;
