@@ -546,15 +546,18 @@ void launch_steepest_cls(int c, int zc, const Fields& F, unsigned grid, uint32_t
                          hipStream_t s) {
     if (grid == 0) return;
     const int rounds = scan_rounds();
+    // packed codes: 512-thread blocks fit their registers at six waves per
+    // SIMD; the other sources keep 256-thread blocks
+    constexpr int NT = Src::kPackedCodes ? kSteepBlock : kBlock;
     launch(PLMSS_KERNEL_STEEPEST, s, [&] {
         if (c != 0)
-            k_steepest<Src, 16, 1, RESOLVE><<<grid, kBlock, 0, s>>>(F, up, dn, rounds);
+            k_steepest<Src, 16, 1, RESOLVE, NT><<<grid, NT, 0, s>>>(F, up, dn, rounds);
         else if (zc == 8)
-            k_steepest<Src, 8, 8, RESOLVE><<<grid, kBlock, 0, s>>>(F, up, dn, rounds);
+            k_steepest<Src, 8, 8, RESOLVE, NT><<<grid, NT, 0, s>>>(F, up, dn, rounds);
         else if (zc == 32)
-            k_steepest<Src, 8, 32, RESOLVE><<<grid, kBlock, 0, s>>>(F, up, dn, rounds);
+            k_steepest<Src, 8, 32, RESOLVE, NT><<<grid, NT, 0, s>>>(F, up, dn, rounds);
         else
-            k_steepest<Src, 8, 16, RESOLVE><<<grid, kBlock, 0, s>>>(F, up, dn, rounds);
+            k_steepest<Src, 8, 16, RESOLVE, NT><<<grid, NT, 0, s>>>(F, up, dn, rounds);
     });
 }
 

@@ -292,17 +292,20 @@ struct SquarePlanes {
     uint8_t tag[3][TY + 1][kTX + 1];  // winner positions: max in bits 0-1, min in bits 2-3
 };
 
-template <class Src, int TY, int ZC, bool RESOLVE>
-__global__ __launch_bounds__(kBlock) void k_steepest(Fields F, uint32_t* up, uint32_t* dn, int rounds) {
+// NT threads per block (eight waves: one row of the tile per wave and plane
+// in 3-D, so that each thread holds half the state of a 256-thread block and
+// twice the waves fit beside the LDS the tile needs).
+template <class Src, int TY, int ZC, bool RESOLVE, int NT>
+__global__ __launch_bounds__(NT, NT >= 512 ? 6 : 1) void k_steepest(Fields F, uint32_t* up, uint32_t* dn, int rounds) {
     using K = typename Src::key_t;
     constexpr bool kSquares = sizeof(K) == 4;
     constexpr bool kPacked = kSquares && Src::kPackedCodes;
-    constexpr int PX = kTX + 2, PY = TY + 2, RPW = TY / kWavesPerBlock;
+    constexpr int PX = kTX + 2, PY = TY + 2, RPW = TY / (NT / kWave);
     constexpr int TV = RESOLVE ? kTX * TY * ZC : 1;
-    constexpr int kLoads = (PY * PX + kBlock - 1) / kBlock;
+    constexpr int kLoads = (PY * PX + NT - 1) / NT;
     constexpr int kSq = (TY + 1) * (kTX + 1);
-    constexpr int kSqLoops = (kSq + kBlock - 1) / kBlock;
-    static_assert(TY % kWavesPerBlock == 0, "rows per wave");
+    constexpr int kSqLoops = (kSq + NT - 1) / NT;
+    static_assert(TY % (NT / kWave) == 0, "rows per wave");
     static_assert((TY & (TY - 1)) == 0, "power-of-two rows");
     static_assert(kTX * TY * ZC < int(kExit), "local indices need 15 bits");
     // raw key planes: the ring of three for the plain scan, one staging plane
@@ -353,7 +356,7 @@ __global__ __launch_bounds__(kBlock) void k_steepest(Fields F, uint32_t* up, uin
     uint32_t ld_off[kLoads];
 #pragma unroll
     for (int k = 0; k < kLoads; ++k) {
-        const int i = t + k * kBlock;
+        const int i = t + k * NT;
         const int r = i / PX, c = i - r * PX;
         const int gx = x0 - 1 + c, gy = y0 - 1 + r;
         ld_in[k] = i < PY * PX && gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny;
@@ -386,7 +389,7 @@ __global__ __launch_bounds__(kBlock) void k_steepest(Fields F, uint32_t* up, uin
         if constexpr (kSquares) {
 #pragma unroll
             for (int k = 0; k < kSqLoops; ++k) {
-                const int i = t + k * kBlock;
+                const int i = t + k * NT;
                 if (i >= kSq) break;
                 const int r = i / (kTX + 1), c = i - r * (kTX + 1);
                 K hi = K(0), lo = ~K(0);
@@ -530,7 +533,7 @@ __global__ __launch_bounds__(kBlock) void k_steepest(Fields F, uint32_t* up, uin
         // the write-out turns local indices into vertex ids through this
         // table (row = plane * TY + row in plane) instead of two 32-bit
         // multiplies per pointer
-        for (int i = t; i < ZC * TY; i += kBlock)
+        for (int i = t; i < ZC * TY; i += NT)
             row_off[RESOLVE ? i : 0] = uint32_t(i / TY) * uint32_t(S) + uint32_t(i % TY) * uint32_t(g.nx);
         __syncthreads();
         // entries of this thread: (lz, row) pairs over the tile's planes; entry
@@ -550,7 +553,7 @@ __global__ __launch_bounds__(kBlock) void k_steepest(Fields F, uint32_t* up, uin
         // waiting for the write before it.  Inside a group a target may be
         // read before its own update; any pointer on the path is a valid
         // value, so this only changes how much each sweep compresses.
-        constexpr int kGroup = 4;
+        constexpr int kGroup = kMine < 4 ? kMine : 4;
         static_assert(kMine % kGroup == 0, "whole groups");
         auto group = [&](int g0, bool rev, bool& ch) {
             if (g0 / RPW >= nz_t) return;
@@ -644,6 +647,8 @@ __global__ __launch_bounds__(kBlock) void k_steepest(Fields F, uint32_t* up, uin
     }
     }  // tiles
 }
+
+constexpr int kSteepBlock = 512;  // threads per neighbour-scan block
 
 inline uint32_t steepest_tiles(int64_t nx, int64_t ny, int64_t nz, int ty, int zc) {
     return uint32_t(((nx + kTX - 1) / kTX) * ((ny + ty - 1) / ty) * ((nz + zc - 1) / zc));
