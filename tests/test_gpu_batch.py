@@ -285,3 +285,29 @@ def test_plan_graph_with_order_fields(torch):
         plain.set(da, outs=plmss._outs_for(da, with_order=True))
     assert e.value.code == plmss.E_ARG
     plain.close()
+
+
+def test_plan_beyond_2_30_vertices_takes_the_wide_id_path(torch):
+    """A plan sized for more than 2^30 vertices numbers its launch's vertices
+    with 31-bit ids, so its cross-tile chase addresses the pointer arrays with
+    64-bit offsets (the path that launches below 2^30 vertices never take).
+    Small fields through such a plan, graph-launched and eager, still give the
+    oracle's labels bit for bit.  (Its workspace is tens of GB: sized for the
+    capacity, not the batch.)"""
+    fs = [fields.smoothed_noise((40, 33, 29), 1.5, seed=71), fields.smoothed_noise((17, 64), 1.2, seed=72),
+          fields.smoothed_noise((300,), 2.0, seed=73), fields.gaussian_blobs((24, 40, 31), seed=74)]
+    ds = [torch.from_numpy(f).cuda() for f in fs]
+    need = plmss.batch_needs(ds)
+    _say("plan with capacity 2^30 + 4096 vertices")
+    plan = plmss.Plan((1 << 30) + 4096, need[1] + 2, need[2] + 10, need[3] + 10)
+    try:
+        for graph in (True, False):
+            outs = plan.set(ds)
+            plan.launch(graph=graph)
+            torch.cuda.synchronize()
+            for i, (f, o) in enumerate(zip(fs, outs)):
+                _check_one(f, o, f"wide-id plan (graph={graph}) field {i} {f.shape}")
+    finally:
+        plan.close()
+        del plan
+        torch.cuda.empty_cache()
