@@ -113,14 +113,14 @@ class Server:
         torch = self.torch
         while self.pending:
             r = self.pending[0]
-            verdict = admission(_numel(r), r.nbytes, self.resident, len(self.admitted), self.max_v, self.budget,
+            decision = admission(_numel(r), r.nbytes, self.resident, len(self.admitted), self.max_v, self.budget,
                                 4 * self.max_f)
-            if verdict == REJECT_BATCH or verdict == REJECT_BUDGET:
+            if decision == REJECT_BATCH or decision == REJECT_BUDGET:
                 self.pending.popleft()
-                r.error = "too large for one batch" if verdict == REJECT_BATCH else "larger than the memory budget"
+                r.error = "too large for one batch" if decision == REJECT_BATCH else "larger than the memory budget"
                 self.rejected += 1
                 continue
-            if verdict == WAIT:
+            if decision == WAIT:
                 break
             self.pending.popleft()
             self.resident += r.nbytes
