@@ -12,8 +12,9 @@ other, and the best values depend on the field's size and shape.
 inputs (coordinate descent: one knob at a time, the others held, each
 candidate timed with HIP events over a few repetitions, the median kept),
 check that every candidate produces exactly the labels of the starting
-configuration, keep a candidate only when it is at least 2% faster, leave the
-winners set, and remember them in a JSON cache keyed
+configuration, keep a candidate only when it is at least 1% faster twice in a
+row (the candidate and the current best are timed again before it replaces
+the best), leave the winners set, and remember them in a JSON cache keyed
 by GPU architecture, element type, workload kind, dimensionality and size
 bucket (log2 of the vertex count).  ``apply`` sets cached values without
 timing anything.
@@ -45,7 +46,7 @@ BATCH_KNOBS = ("persist_blocks", "scan_depth", "scan_rounds", "sort_workers")
 
 # a candidate replaces the current setting only when it is this much faster,
 # so that timing noise does not flip settings from run to run
-MIN_GAIN = 0.02
+MIN_GAIN = 0.01
 
 _lock = threading.Lock()
 
@@ -144,7 +145,17 @@ def _descend(torch, knobs, run, result, reps: int, log=None):
             if log:
                 log(f"tune {cand}: {ms:.3f} ms")
             if ms < best_ms * (1.0 - MIN_GAIN):
-                best, best_ms = cand, ms
+                # confirm: time the current best and the candidate once more
+                tune_set(**best)
+                again_best = _time(torch, run, reps)
+                tune_set(**cand)
+                again = _time(torch, run, reps)
+                if log:
+                    log(f"tune confirm {cand}: {again:.3f} ms against {again_best:.3f} ms")
+                if again < again_best * (1.0 - MIN_GAIN):
+                    best, best_ms = cand, min(ms, again)
+                else:
+                    best_ms = min(best_ms, again_best)
         tune_set(**best)
     return best, best_ms, base_ms, trials
 
