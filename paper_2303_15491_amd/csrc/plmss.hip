@@ -512,8 +512,12 @@ PairList sort_pairs(int bits, const Work& w, hipStream_t s) {
     const int passes = (bits + kRadixBits - 1) / kRadixBits;
     uint64_t* keys[2] = {reinterpret_cast<uint64_t*>(w.keys[1]), reinterpret_cast<uint64_t*>(w.keys[0])};
     uint32_t* vals[2] = {w.vals[0], w.vals[1]};
-    int cur = 0;
-    for (int p = 0; p < passes; ++p) {
+    // the listed records' values are their own indices: the first pass
+    // generates them instead of reading them
+    radix_pass(IndexValSrc<uint64_t>{keys[0]}, ArrayDst<uint64_t>{keys[1], vals[1]}, w.counters, 0, sort_workers(),
+               0, false, w, nullptr, s);
+    int cur = 1;
+    for (int p = 1; p < passes; ++p) {
         radix_pass(ArraySrc<uint64_t>{keys[cur], vals[cur]}, ArrayDst<uint64_t>{keys[cur ^ 1], vals[cur ^ 1]},
                    w.counters, 0, sort_workers(), kRadixBits * p, false, w, nullptr, s);
         cur ^= 1;
@@ -586,17 +590,17 @@ void launch_chase_cls(int c, const Fields& F, unsigned grid, uint32_t* U, uint32
     const bool o32 = bn <= 30;
     launch(PLMSS_KERNEL_JUMP, s, [&] {
         if (c == 0 && o32)
-            k_chase<JTile3, CHASE, true><<<grid, kChaseBlock, 0, s>>>(F, U, D, bn, rec, w.vals[0], w.counters + 0);
+            k_chase<JTile3, CHASE, true><<<grid, kChaseBlock, 0, s>>>(F, U, D, bn, rec, w.counters + 0);
         else if (c == 0)
-            k_chase<JTile3, CHASE, false><<<grid, kChaseBlock, 0, s>>>(F, U, D, bn, rec, w.vals[0], w.counters + 0);
+            k_chase<JTile3, CHASE, false><<<grid, kChaseBlock, 0, s>>>(F, U, D, bn, rec, w.counters + 0);
         else if (c == 1 && o32)
-            k_chase<JTile2, CHASE, true><<<grid, kChaseBlock, 0, s>>>(F, U, D, bn, rec, w.vals[0], w.counters + 0);
+            k_chase<JTile2, CHASE, true><<<grid, kChaseBlock, 0, s>>>(F, U, D, bn, rec, w.counters + 0);
         else if (c == 1)
-            k_chase<JTile2, CHASE, false><<<grid, kChaseBlock, 0, s>>>(F, U, D, bn, rec, w.vals[0], w.counters + 0);
+            k_chase<JTile2, CHASE, false><<<grid, kChaseBlock, 0, s>>>(F, U, D, bn, rec, w.counters + 0);
         else if (o32)
-            k_chase<JTile1, CHASE, true><<<grid, kChaseBlock, 0, s>>>(F, U, D, bn, rec, w.vals[0], w.counters + 0);
+            k_chase<JTile1, CHASE, true><<<grid, kChaseBlock, 0, s>>>(F, U, D, bn, rec, w.counters + 0);
         else
-            k_chase<JTile1, CHASE, false><<<grid, kChaseBlock, 0, s>>>(F, U, D, bn, rec, w.vals[0], w.counters + 0);
+            k_chase<JTile1, CHASE, false><<<grid, kChaseBlock, 0, s>>>(F, U, D, bn, rec, w.counters + 0);
     });
 }
 

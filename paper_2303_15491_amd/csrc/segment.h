@@ -663,9 +663,9 @@ inline uint32_t steepest_tiles(int64_t nx, int64_t ny, int64_t nz, int ty, int z
 // marked extremum.  It writes desc/asc, then lists the tile's distinct
 // (asc, desc) pairs through an LDS hash set: the tile takes a run of
 // consecutive record indices from a launch-wide counter (one atomic add per
-// tile), writes each pair key (asc << bn) | desc to rec_keys and its record
-// index to rec_vals, and stores each vertex's record index in ms[v] (replaced
-// by the MS id later).  MS regions are a few vertices across, so a 3-D tile
+// tile), writes each pair key (asc << bn) | desc to rec_keys at its record
+// index (the pair sort generates the indices as the keys' values), and stores
+// each vertex's record index in ms[v] (replaced by the MS id later).  MS regions are a few vertices across, so a 3-D tile
 // lists far fewer pairs than a row of the same size would.
 constexpr int kJV = 2048;            // vertices per tile
 constexpr int kJPer = kJV / kBlock;  // per thread (256-thread blocks)
@@ -724,7 +724,7 @@ __device__ __forceinline__ void jtile_xyz(const FieldDesc& fd, uint32_t lt, int 
 // arrays are addressed by 32-bit byte offsets.
 template <class T, bool CHASE, bool O32>
 __global__ __launch_bounds__(kChaseBlock, 8) void k_chase(Fields F, uint32_t* U, uint32_t* D, int bn,
-                                                  uint64_t* rec_keys, uint32_t* rec_vals, uint32_t* rec_count) {
+                                                  uint64_t* rec_keys, uint32_t* rec_count) {
     __shared__ uint64_t table[kHash];
     __shared__ uint16_t dense[kHash];
     __shared__ uint32_t tmp[kChaseWaves];
@@ -880,7 +880,6 @@ __global__ __launch_bounds__(kChaseBlock, 8) void k_chase(Fields F, uint32_t* U,
                     j + __builtin_amdgcn_mbcnt_hi(uint32_t(occ >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(occ), 0u));
                 dense[sl] = uint16_t(jj);
                 rec_keys[base + jj] = k;
-                rec_vals[base + jj] = base + jj;
             }
             j += uint32_t(__popcll(occ));
         }

@@ -69,6 +69,17 @@ struct ArraySrc {
     __device__ __forceinline__ static bool nan_key(key_t) { return false; }
 };
 
+// Keys whose value is their own index (a list in its original order): the
+// value is generated, not read.
+template <typename K>
+struct IndexValSrc {
+    using key_t = K;
+    const K* keys;
+    __device__ __forceinline__ K key(uint32_t i) const { return keys[i]; }
+    __device__ __forceinline__ uint32_t val(uint32_t i) const { return i; }
+    __device__ __forceinline__ static bool nan_key(key_t) { return false; }
+};
+
 // 32-bit keys and their ids packed in one word, key in the high half: one
 // load and one store per item, and one output stream per digit.
 struct PackedSrc {
@@ -96,6 +107,11 @@ template <typename K>
 __device__ __forceinline__ void load_item(const ArraySrc<K>& s, uint32_t i, K& k, uint32_t& v) {
     k = s.keys[i];
     v = s.vals[i];
+}
+template <typename K>
+__device__ __forceinline__ void load_item(const IndexValSrc<K>& s, uint32_t i, K& k, uint32_t& v) {
+    k = s.keys[i];
+    v = i;
 }
 __device__ __forceinline__ void load_item(const PackedSrc& s, uint32_t i, uint32_t& k, uint32_t& v) {
     const uint64_t x = s.kv[i];
