@@ -342,21 +342,25 @@ __global__ __launch_bounds__(kBlock) void k_radix_digit_scan(uint32_t* hist, uin
     if (threadIdx.x == 0 && sg == 0) dtotal[d] = nseg > 1 ? total : run;
 }
 
+// The per-wave digit counters (and then offsets) hold at most a wave's 1024
+// keys of a tile, and a digit's start and count in the tile at most 4096: two
+// 16-bit halves share one word (waves 2i and 2i + 1; start low, count high),
+// which with 64-bit keys brings the block to 52 KB of LDS, three per CU.
 template <typename K>
 struct ScatterSmem {
     K keys[kTile];
     uint32_t vals[kTile];
-    uint32_t wcnt[kWavesPerBlock][kRadix];
+    uint32_t wcnt[kWavesPerBlock / 2][kRadix];
     uint32_t run[kRadix];
-    uint32_t tstart[kRadix];
-    uint32_t tcount[kRadix];
+    uint32_t tspan[kRadix];
     uint32_t tmp[kWavesPerBlock];
 };
+static_assert(kItems * kWave < (1 << 16) && kTile < (1 << 16), "16-bit halves");
 
-// 32-bit keys: four blocks per CU (the LDS allows four; the register budget
-// of the unrolled tile is held to it)
+// 32-bit keys: four blocks per CU, 64-bit keys three (the LDS allows that
+// many; the register budget of the unrolled tile is held to it)
 template <class Src, class Dst>
-__global__ __launch_bounds__(kBlock, sizeof(typename Src::key_t) == 4 ? 4 : 2) void k_radix_scatter(Src src, Dst dst,
+__global__ __launch_bounds__(kBlock, sizeof(typename Src::key_t) == 4 ? 4 : 3) void k_radix_scatter(Src src, Dst dst,
                                                           const uint32_t* count_ptr, uint32_t n,
                                                           int shift, const uint32_t* hist,
                                                           const uint32_t* dtotal) {
@@ -385,8 +389,9 @@ __global__ __launch_bounds__(kBlock, sizeof(typename Src::key_t) == 4 ? 4 : 2) v
     auto step = [&](uint32_t tile) {
         const uint32_t tsize = min(uint32_t(kTile), hi - tile);
 #pragma unroll
-        for (int i = 0; i < kWavesPerBlock; ++i) sm.wcnt[i][t] = 0;
+        for (int i = 0; i < kWavesPerBlock / 2; ++i) sm.wcnt[i][t] = 0;
         const uint32_t wbase = tile + uint32_t(w) * kWave * kItems + lane;
+        const uint32_t half = 16u * uint32_t(w & 1);  // this wave's half of its counter words
         __syncthreads();
         // rank inside the wave: the highest lane of each digit group adds the
         // group's size to the wave's counter and gets the count before it;
@@ -404,7 +409,8 @@ __global__ __launch_bounds__(kBlock, sizeof(typename Src::key_t) == 4 ? 4 : 2) v
             const int leader = peers ? top_lane(peers) : lane;
             local[i] = uint32_t(__popcll(peers & lt)) | (uint32_t(leader) << 8);
             prior[i] = 0;
-            if (valid && leader == lane) prior[i] = atomicAdd(&sm.wcnt[w][d], uint32_t(__popcll(peers)));
+            if (valid && leader == lane)
+                prior[i] = (atomicAdd(&sm.wcnt[w >> 1][d], uint32_t(__popcll(peers)) << half) >> half) & 0xffffu;
         }
 #pragma unroll
         for (int i = 0; i < kItems; ++i)
@@ -414,17 +420,16 @@ __global__ __launch_bounds__(kBlock, sizeof(typename Src::key_t) == 4 ? 4 : 2) v
             uint32_t c[kWavesPerBlock], sum = 0;
 #pragma unroll
             for (int i = 0; i < kWavesPerBlock; ++i) {
-                c[i] = sm.wcnt[i][t];
+                c[i] = (sm.wcnt[i >> 1][t] >> (16 * (i & 1))) & 0xffffu;
                 sum += c[i];
             }
             uint32_t ttot;
             uint32_t acc = block_exclusive_scan(sum, sm.tmp, &ttot);
-            sm.tstart[t] = acc;
-            sm.tcount[t] = sum;
+            sm.tspan[t] = acc | (sum << 16);
 #pragma unroll
-            for (int i = 0; i < kWavesPerBlock; ++i) {
-                sm.wcnt[i][t] = acc;
-                acc += c[i];
+            for (int i = 0; i < kWavesPerBlock; i += 2) {
+                sm.wcnt[i >> 1][t] = acc | ((acc + c[i]) << 16);
+                acc += c[i] + c[i + 1];
             }
         }
         __syncthreads();
@@ -432,7 +437,8 @@ __global__ __launch_bounds__(kBlock, sizeof(typename Src::key_t) == 4 ? 4 : 2) v
         for (int i = 0; i < kItems; ++i) {
             const uint32_t idx = wbase + uint32_t(i) * kWave;
             if (idx < hi) {
-                const uint32_t p = sm.wcnt[w][digit_of(key[i], shift)] + local[i];
+                const uint32_t p =
+                    ((sm.wcnt[w >> 1][digit_of(key[i], shift)] >> half) & 0xffffu) + local[i];
                 sm.keys[p] = key[i];
                 sm.vals[p] = val[i];
             }
@@ -449,10 +455,10 @@ __global__ __launch_bounds__(kBlock, sizeof(typename Src::key_t) == 4 ? 4 : 2) v
             const uint32_t j = min(uint32_t(i) * kBlock + t, tsize - 1u);
             const K k = sm.keys[j];
             const uint32_t d = digit_of(k, shift);
-            dst.put(sm.run[d] + (j - sm.tstart[d]), k, sm.vals[j]);
+            dst.put(sm.run[d] + (j - (sm.tspan[d] & 0xffffu)), k, sm.vals[j]);
         }
         __syncthreads();
-        sm.run[t] += sm.tcount[t];
+        sm.run[t] += sm.tspan[t] >> 16;
     };
     // the first tile is peeled off, so that every pass through the loop
     // starts with the same memory operations in flight
