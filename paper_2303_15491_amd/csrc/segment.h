@@ -296,7 +296,7 @@ struct SquarePlanes {
 // in 3-D, so that each thread holds half the state of a 256-thread block and
 // twice the waves fit beside the LDS the tile needs).
 template <class Src, int TY, int ZC, bool RESOLVE, int NT>
-__global__ __launch_bounds__(NT, NT >= 512 ? 6 : 1) void k_steepest(Fields F, uint32_t* up, uint32_t* dn, int rounds) {
+__global__ __launch_bounds__(NT, NT >= 512 && ZC <= 16 ? 6 : 1) void k_steepest(Fields F, uint32_t* up, uint32_t* dn, int rounds) {
     using K = typename Src::key_t;
     constexpr bool kSquares = sizeof(K) == 4;
     constexpr bool kPacked = kSquares && Src::kPackedCodes;
