@@ -49,12 +49,6 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
     return (uint64_t(1) << lane_id()) - 1;
 }
 
-// Number of set bits of m below this lane (the hardware's masked bit count,
-// with no lane mask held in registers).
-__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
-    return __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
-}
-
 // Order-preserving integer keys of IEEE values: unsigned comparison of keys is
 // the IEEE order, with -0 mapped to +0 so that the two compare equal (ties are
 // then decided by vertex id).  NaNs are reported separately.  The keys of all
