@@ -84,9 +84,9 @@ def kernel_source_digest() -> str:
 # The kernel (as rocprofv3 names it) each trace kind launches on the headline
 # workload: one 3-D float32 field with its order field, default scan tiles.
 HEADLINE_SYMBOLS = {
-    "jump": "k_chase<JTile<32, 8, 8>, true, true>",
+    "jump": "k_chase<JTile<32, 8, 8>, true, true, true>",
     "steepest": "k_steepest<RankOrderPacked, 8, 16, true, 512>",
-    "ms_final": "k_ms_final<JTile<32, 8, 8> >",
+    "ms_final": "k_ms_final<JTile<32, 8, 8>, true>",
     "order_scatter": "k_radix_scatter<PackedSrc, PackedDst>",
     "order_first": "k_radix_scatter<FieldSrc<float, unsigned int>, PackedDst>",
     "order_last": "k_rank_partition<PackedSrc>",

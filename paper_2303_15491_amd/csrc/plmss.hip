@@ -513,12 +513,13 @@ PairList sort_pairs(int bits, const Work& w, hipStream_t s) {
     uint64_t* keys[2] = {reinterpret_cast<uint64_t*>(w.keys[1]), reinterpret_cast<uint64_t*>(w.keys[0])};
     uint32_t* vals[2] = {w.vals[0], w.vals[1]};
     // the listed records' values are their own indices: the first pass
-    // generates them instead of reading them
-    radix_pass(IndexValSrc<uint64_t>{keys[0]}, ArrayDst<uint64_t>{keys[1], vals[1]}, w.counters, 0, sort_workers(),
-               0, false, w, nullptr, s);
+    // generates them instead of reading them.  The list is small next to
+    // the field and is read with cached loads (pass_load).
+    radix_pass(IndexValSrc<uint64_t, false>{keys[0]}, ArrayDst<uint64_t>{keys[1], vals[1]}, w.counters, 0,
+               sort_workers(), 0, false, w, nullptr, s);
     int cur = 1;
     for (int p = 1; p < passes; ++p) {
-        radix_pass(ArraySrc<uint64_t>{keys[cur], vals[cur]}, ArrayDst<uint64_t>{keys[cur ^ 1], vals[cur ^ 1]},
+        radix_pass(ArraySrc<uint64_t, false>{keys[cur], vals[cur]}, ArrayDst<uint64_t>{keys[cur ^ 1], vals[cur ^ 1]},
                    w.counters, 0, sort_workers(), kRadixBits * p, false, w, nullptr, s);
         cur ^= 1;
     }
@@ -581,6 +582,11 @@ void launch_steepest_any(int c, int zc, const Fields& F, unsigned grid, int32_t 
         launch_steepest_cls<RESOLVE, FieldOrder<double, uint64_t>>(c, zc, F, grid, up, dn, s);
 }
 
+// A launch over one field whose label rows are whole cache lines (the
+// kernels' STREAM forms, segment.h kWholeLines); 3-D fields only, the shape
+// that the 512^3 and batch workloads take.
+bool whole_lines(const Fields& F) { return F.table == nullptr && (F.one.flags & kWholeLines); }
+
 template <bool CHASE>
 void launch_chase_cls(int c, const Fields& F, unsigned grid, uint32_t* U, uint32_t* D, int bn, const Work& w,
                       hipStream_t s) {
@@ -589,7 +595,9 @@ void launch_chase_cls(int c, const Fields& F, unsigned grid, uint32_t* U, uint32
     // ids below 2^30: 32-bit byte offsets address every array of the chase
     const bool o32 = bn <= 30;
     launch(PLMSS_KERNEL_JUMP, s, [&] {
-        if (c == 0 && o32)
+        if (c == 0 && o32 && whole_lines(F))
+            k_chase<JTile3, CHASE, true, true><<<grid, kChaseBlock, 0, s>>>(F, U, D, bn, rec, w.counters + 0);
+        else if (c == 0 && o32)
             k_chase<JTile3, CHASE, true><<<grid, kChaseBlock, 0, s>>>(F, U, D, bn, rec, w.counters + 0);
         else if (c == 0)
             k_chase<JTile3, CHASE, false><<<grid, kChaseBlock, 0, s>>>(F, U, D, bn, rec, w.counters + 0);
@@ -607,7 +615,9 @@ void launch_chase_cls(int c, const Fields& F, unsigned grid, uint32_t* U, uint32
 void launch_ms_final_cls(int c, const Fields& F, unsigned grid, const Work& w, hipStream_t s) {
     if (grid == 0) return;
     launch(PLMSS_KERNEL_MS_FINAL, s, [&] {
-        if (c == 0)
+        if (c == 0 && whole_lines(F))
+            k_ms_final<JTile3, true><<<grid, kBlock, 0, s>>>(F, w.rank_of, w.fbase);
+        else if (c == 0)
             k_ms_final<JTile3><<<grid, kBlock, 0, s>>>(F, w.rank_of, w.fbase);
         else if (c == 1)
             k_ms_final<JTile2><<<grid, kBlock, 0, s>>>(F, w.rank_of, w.fbase);
@@ -796,6 +806,9 @@ FieldDesc desc_of(const plmss_job& j, uint32_t vbase, uint32_t sbase, uint32_t j
     d.vbase = vbase;
     d.sbase = sbase;
     d.jbase = jbase;
+    // whole 128-byte lines per row of the label arrays (segment.h, kWholeLines)
+    const auto line = [](const void* p) { return p == nullptr || reinterpret_cast<uintptr_t>(p) % 128 == 0; };
+    d.flags = (j.dims.nx % 32 == 0 && line(j.asc) && line(j.desc) && line(j.ms)) ? kWholeLines : 0u;
     return d;
 }
 

@@ -74,7 +74,20 @@ struct FieldDesc {
     uint32_t sbase;    // first steepest tile (within its shape class)
     uint32_t jbase;    // first chase tile (within its shape class)
     uint32_t index;    // position among all fields of the launch
+    uint32_t flags;    // kWholeLines or 0
 };
+
+// The field's label arrays (asc, desc, ms) start on a 128-byte line and its
+// rows are whole lines (nx a multiple of 32 vertices): then every row of a
+// chase tile covers whole lines, and a launch over such a field alone takes
+// the kernels' STREAM forms, whose label stores (chase) and record loads (MS
+// write-back) bypass the caches (non-temporal: labels are written once,
+// record indices read once).  Otherwise neighbouring tiles share lines, and
+// non-temporal accesses would move each shared line as two partial
+// transfers instead of letting the cache merge them.  (A compile-time
+// choice: a run-time branch between the two forms of the same access is
+// merged by the compiler into the plain one.)
+constexpr uint32_t kWholeLines = 1u;
 
 // The fields of a launch: a device table (batches) or a single descriptor
 // passed by value.  Tile totals are host values, or device values for launches
@@ -106,6 +119,7 @@ __device__ __forceinline__ FieldDesc load_desc(const FieldDesc* table, uint32_t 
     d.sbase = g->sbase;
     d.jbase = g->jbase;
     d.index = g->index;
+    d.flags = g->flags;
     return d;
 }
 
@@ -631,8 +645,10 @@ __global__ __launch_bounds__(NT, NT >= 512 && ZC <= 16 ? 6 : 1) void k_steepest(
                 const uint32_t own = lp[li];
                 const uint32_t pu = own & 0xffffu, pd = own >> 16;
                 const uint32_t qu = lp[pu & (kExit - 1)] & 0xffffu, qd = lp[pd & (kExit - 1)] >> 16;
-                up[v] = resolve(v, pu, qu);
-                dn[v] = resolve(v, pd, qd);
+                // whole rows of a tile, written once: streamed past the
+                // caches (non-temporal), which the field's loads then keep
+                __builtin_nontemporal_store(resolve(v, pu, qu), up + v);
+                __builtin_nontemporal_store(resolve(v, pd, qd), dn + v);
             }
         }
     }
@@ -721,8 +737,8 @@ __device__ __forceinline__ void jtile_xyz(const FieldDesc& fd, uint32_t lt, int 
 // CHASE: labels from the tile-compressed pointers U/D (written back as they
 // are followed).  Otherwise the labels are read from the field's desc/asc.
 // O32: every vertex id of the launch is below 2^30, so U, D and the label
-// arrays are addressed by 32-bit byte offsets.
-template <class T, bool CHASE, bool O32>
+// arrays are addressed by 32-bit byte offsets.  STREAM: see kWholeLines.
+template <class T, bool CHASE, bool O32, bool STREAM = false>
 __global__ __launch_bounds__(kChaseBlock, 8) void k_chase(Fields F, uint32_t* U, uint32_t* D, int bn,
                                                   uint64_t* rec_keys, uint32_t* rec_count) {
     __shared__ uint64_t table[kHash];
@@ -811,8 +827,14 @@ __global__ __launch_bounds__(kChaseBlock, 8) void k_chase(Fields F, uint32_t* U,
                 pu[i] &= ~kMark;
                 pd[i] &= ~kMark;
                 if (ok[i]) {
-                    *gelem<O32>(fd.desc, lv[i]) = int32_t(pu[i] - fd.vbase);
-                    *gelem<O32>(fd.asc, lv[i]) = int32_t(pd[i] - fd.vbase);
+                    const int32_t dv = int32_t(pu[i] - fd.vbase), av = int32_t(pd[i] - fd.vbase);
+                    if constexpr (STREAM) {
+                        __builtin_nontemporal_store(dv, gelem<O32>(fd.desc, lv[i]));
+                        __builtin_nontemporal_store(av, gelem<O32>(fd.asc, lv[i]));
+                    } else {
+                        *gelem<O32>(fd.desc, lv[i]) = dv;
+                        *gelem<O32>(fd.asc, lv[i]) = av;
+                    }
                 }
             }
             if (pending && fd.info) gmem(fd.info)[0] = -7;  // PLMSS_E_NOCONV
@@ -1020,8 +1042,8 @@ __global__ __launch_bounds__(kBlock) void k_rank_apply(const uint64_t* keys, con
 
 // ms[v] = MS id of its listed pair: rank_of[record] minus the field's first
 // id, with the record index in ms[v] on entry.  Runs over the chase tiles, so
-// every block knows its field.
-template <class T>
+// every block knows its field.  STREAM: see kWholeLines.
+template <class T, bool STREAM = false>
 __global__ __launch_bounds__(kBlock) void k_ms_final(Fields F, const uint32_t* rank_of, const uint32_t* fbase) {
     uint32_t tfirst, tlast;
     block_tiles(F.dev_tiles ? gmem(F.dev_tiles)[1] : F.j_tiles, &tfirst, &tlast);
@@ -1047,8 +1069,14 @@ __global__ __launch_bounds__(kBlock) void k_ms_final(Fields F, const uint32_t* r
             st.ok[i] = x < fd.nx && y < fd.ny && z < fd.nz;
             st.lv[i] = (uint32_t(z) * uint32_t(fd.ny) + uint32_t(y)) * uint32_t(fd.nx) + uint32_t(x);
             // vertex 0 of the field stands in for lanes past its edge, so the
-            // loads need no branch and issue together
-            st.sl[i] = uint32_t(gmem(fd.ms)[st.ok[i] ? st.lv[i] : 0u]);
+            // loads need no branch and issue together; in the STREAM form
+            // each record index is read past the caches, so that the
+            // gathered ranks stay cached
+            const auto* p = gmem(fd.ms) + (st.ok[i] ? st.lv[i] : 0u);
+            if constexpr (STREAM)
+                st.sl[i] = uint32_t(__builtin_nontemporal_load(p));
+            else
+                st.sl[i] = uint32_t(*p);
         }
     };
     Stage cur, nxt;
