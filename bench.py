@@ -63,7 +63,7 @@ KIND_KNOBS = {"steepest": ("scan_depth", "scan_rounds", "packed_codes"), "jump":
 for _k in ("order_first", "order_scatter", "order_last", "order_regroup", "order_invert", "order_hist"):
     KIND_KNOBS[_k] = ("order_workers", "order_invert", "order_packed", "order_concurrent")
 for _k in ("radix_hist", "radix_scatter", "radix_digit_scan", "pair_rank"):
-    KIND_KNOBS[_k] = ("sort_workers",)
+    KIND_KNOBS[_k] = ("sort_workers", "pair_stream")
 
 
 def kernel_source_digest() -> str:

@@ -386,6 +386,12 @@ const char* plmss_kernel_name(int32_t kind);
  *                              and candidates are compared by plain max/min;
  *                              0 = ranks and codes apart (the form used above
  *                              that size).
+ *   PLMSS_TUNE_PAIR_STREAM     loads of the MS pair sort: 0 = cached, 1 =
+ *                              non-temporal (streamed past the caches), 2
+ *                              (default) = streamed for batches and plans,
+ *                              whose pair lists are long, and cached for a
+ *                              single field, whose list usually stays in
+ *                              the memory-side cache between passes.
  *   PLMSS_TUNE_SCAN_ROUNDS     in-tile path-compression sweeps of the
  *                              neighbour scan (1..8, default 3); what they
  *                              leave unfinished the cross-tile chase follows.
@@ -412,7 +418,8 @@ const char* plmss_kernel_name(int32_t kind);
 #define PLMSS_TUNE_SCAN_ROUNDS 6
 #define PLMSS_TUNE_ORDER_CONCURRENT 7
 #define PLMSS_TUNE_PACKED_CODES 8
-#define PLMSS_TUNE_KNOBS 9
+#define PLMSS_TUNE_PAIR_STREAM 9
+#define PLMSS_TUNE_KNOBS 10
 int32_t plmss_tune_set(int32_t knob, int64_t value);
 int64_t plmss_tune_get(int32_t knob);
 

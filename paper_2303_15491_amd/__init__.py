@@ -94,7 +94,7 @@ _SIGNATURES = {
 # Launch-shape knobs (plmss_tune_*): name -> id.
 KNOBS = {"order_workers": 0, "order_invert": 1, "sort_workers": 2, "persist_blocks": 3, "scan_depth": 4,
          "order_packed": 5, "scan_rounds": 6, "order_concurrent": 7,
-         "packed_codes": 8}
+         "packed_codes": 8, "pair_stream": 9}
 
 
 def library():

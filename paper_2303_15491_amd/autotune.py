@@ -38,11 +38,12 @@ SPACE = {
     "sort_workers": [512, 256, 1024, 2048, 4096],
     "scan_depth": [8, 16, 32],
     "persist_blocks": [512, 1024, 2048, 4096, 8192, 16384],
+    "pair_stream": [2, 0, 1],
 }
 
-SEGMENT_KNOBS = ("scan_depth", "scan_rounds", "sort_workers")
+SEGMENT_KNOBS = ("scan_depth", "scan_rounds", "sort_workers", "pair_stream")
 ORDER_KNOBS = ("order_workers", "order_invert", "order_packed")
-BATCH_KNOBS = ("persist_blocks", "scan_depth", "scan_rounds", "sort_workers")
+BATCH_KNOBS = ("persist_blocks", "scan_depth", "scan_rounds", "sort_workers", "pair_stream")
 
 # a candidate replaces the current setting only when it is this much faster,
 # so that timing noise does not flip settings from run to run

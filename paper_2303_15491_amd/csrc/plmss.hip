@@ -38,10 +38,11 @@ constexpr KnobRange kKnobs[PLMSS_TUNE_KNOBS] = {
     {1, 8, kResolveRounds, false, false},      // SCAN_ROUNDS: in-tile jumping sweeps
     {1, 1, 0, true, false},                    // ORDER_CONCURRENT: order field on a second stream
     {1, 1, 1, true, false},                    // PACKED_CODES: rank and code in one word when they fit
+    {0, 2, 2, false, false},                   // PAIR_STREAM: 0 cached, 1 streamed, 2 streamed for batches
 };
 std::atomic<int64_t> g_knob[PLMSS_TUNE_KNOBS] = {kKnobs[0].def, kKnobs[1].def, kKnobs[2].def,
                                                  kKnobs[3].def, kKnobs[4].def, kKnobs[5].def,
-                                                 kKnobs[6].def, kKnobs[7].def, kKnobs[8].def};
+                                                 kKnobs[6].def, kKnobs[7].def, kKnobs[8].def, kKnobs[9].def};
 
 int64_t knob(int k) { return g_knob[k].load(std::memory_order_relaxed); }
 unsigned sort_workers() { return unsigned(knob(PLMSS_TUNE_SORT_WORKERS)); }
@@ -508,22 +509,34 @@ struct PairList {
     const uint32_t* vals;
 };
 
-PairList sort_pairs(int bits, const Work& w, hipStream_t s) {
+template <bool NT>
+PairList sort_pairs_t(int bits, const Work& w, hipStream_t s) {
     const int passes = (bits + kRadixBits - 1) / kRadixBits;
     uint64_t* keys[2] = {reinterpret_cast<uint64_t*>(w.keys[1]), reinterpret_cast<uint64_t*>(w.keys[0])};
     uint32_t* vals[2] = {w.vals[0], w.vals[1]};
     // the listed records' values are their own indices: the first pass
-    // generates them instead of reading them.  The list is small next to
-    // the field and is read with cached loads (pass_load).
-    radix_pass(IndexValSrc<uint64_t, false>{keys[0]}, ArrayDst<uint64_t>{keys[1], vals[1]}, w.counters, 0,
+    // generates them instead of reading them
+    radix_pass(IndexValSrc<uint64_t, NT>{keys[0]}, ArrayDst<uint64_t>{keys[1], vals[1]}, w.counters, 0,
                sort_workers(), 0, false, w, nullptr, s);
     int cur = 1;
     for (int p = 1; p < passes; ++p) {
-        radix_pass(ArraySrc<uint64_t, false>{keys[cur], vals[cur]}, ArrayDst<uint64_t>{keys[cur ^ 1], vals[cur ^ 1]},
+        radix_pass(ArraySrc<uint64_t, NT>{keys[cur], vals[cur]}, ArrayDst<uint64_t>{keys[cur ^ 1], vals[cur ^ 1]},
                    w.counters, 0, sort_workers(), kRadixBits * p, false, w, nullptr, s);
         cur ^= 1;
     }
     return {keys[cur], vals[cur]};
+}
+
+// The pair list's loads (pass_load): streamed when the list outgrows the
+// memory-side cache, as a batch's does (the noisy 64-field batch lists 22 M
+// pairs, 0.5 GB with their ping-pong copies: scatters 1.41 -> 1.07 ms), and
+// cached otherwise (a 512^3 field lists 8 M: streamed loads cost its
+// scatters 5%).  The length is known only on the device, so the choice
+// follows the launch (PLMSS_TUNE_PAIR_STREAM).
+PairList sort_pairs(int bits, bool batch, const Work& w, hipStream_t s) {
+    const int64_t mode = knob(PLMSS_TUNE_PAIR_STREAM);
+    if (mode == 1 || (mode == 2 && batch)) return sort_pairs_t<true>(bits, w, s);
+    return sort_pairs_t<false>(bits, w, s);
 }
 
 // ---- one launch over a set of fields -------------------------------------------------------
@@ -629,7 +642,7 @@ void launch_ms_final_cls(int c, const Fields& F, unsigned grid, const Work& w, h
 // MS ids from the pairs the chase listed: sort, rank, per-field bases,
 // relabel.
 void ms_from_pairs(const LaunchSet& L, const Work& w, hipStream_t s) {
-    const PairList sorted = sort_pairs(2 * L.bn, w, s);
+    const PairList sorted = sort_pairs(2 * L.bn, L.all.table != nullptr, w, s);
     const uint64_t* sk = sorted.keys;
     const unsigned nw = sort_workers();
     launch(PLMSS_KERNEL_RANK, s, [&] { k_rank_reduce<<<nw, kBlock, 0, s>>>(sk, w.counters + 0, w.partial); });

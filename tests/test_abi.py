@@ -133,11 +133,14 @@ def test_tuning_knobs_validate_ranges():
         assert lib.plmss_tune_set(plmss.KNOBS["order_invert"], 65) == plmss.E_ARG
         assert lib.plmss_tune_set(plmss.KNOBS["scan_rounds"], 0) == plmss.E_ARG
         assert lib.plmss_tune_set(plmss.KNOBS["packed_codes"], 2) == plmss.E_ARG
+        assert lib.plmss_tune_set(plmss.KNOBS["pair_stream"], 3) == plmss.E_ARG
+        assert lib.plmss_tune_set(plmss.KNOBS["pair_stream"], -1) == plmss.E_ARG
+        assert saved["pair_stream"] == 2
         plmss.tune_set(order_workers=0, order_invert=0, sort_workers=512, persist_blocks=4096, scan_depth=8,
-                       order_packed=1, scan_rounds=1, order_concurrent=0, packed_codes=1)
+                       order_packed=1, scan_rounds=1, order_concurrent=0, packed_codes=1, pair_stream=0)
         assert plmss.tune_get() == {"order_workers": 0, "order_invert": 0, "sort_workers": 512,
                                     "persist_blocks": 4096, "scan_depth": 8, "order_packed": 1, "scan_rounds": 1,
-                                    "order_concurrent": 0, "packed_codes": 1}
+                                    "order_concurrent": 0, "packed_codes": 1, "pair_stream": 0}
         with pytest.raises(plmss.PlmssError):
             plmss.tune_set(order_workers=10)
         with pytest.raises(KeyError):

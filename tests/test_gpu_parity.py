@@ -93,6 +93,7 @@ def test_ragged_tiles_both_paths(torch, shape):
     {"scan_rounds": 1}, {"scan_rounds": 8, "scan_depth": 32}, {"scan_rounds": 2, "scan_depth": 8},
     {"order_concurrent": 1}, {"order_concurrent": 1, "order_packed": 0},
     {"packed_codes": 0}, {"packed_codes": 0, "scan_depth": 8},
+    {"pair_stream": 1}, {"pair_stream": 0, "sort_workers": 64},
 ])
 def test_launch_shapes_keep_results(torch, knobs):
     """Every launch-shape knob setting gives the oracle's labels (tile depths
