@@ -608,8 +608,8 @@ void launch_chase_cls(int c, const Fields& F, unsigned grid, uint32_t* U, uint32
     // ids below 2^30: 32-bit byte offsets address every array of the chase
     const bool o32 = bn <= 30;
     launch(PLMSS_KERNEL_JUMP, s, [&] {
-        if (c == 0 && o32 && whole_lines(F))
-            k_chase<JTile3, CHASE, true, true><<<grid, kChaseBlock, 0, s>>>(F, U, D, bn, rec, w.counters + 0);
+        if (CHASE && c == 0 && o32 && whole_lines(F))
+            k_chase<JTile3, CHASE, true, CHASE><<<grid, kChaseBlock, 0, s>>>(F, U, D, bn, rec, w.counters + 0);
         else if (c == 0 && o32)
             k_chase<JTile3, CHASE, true><<<grid, kChaseBlock, 0, s>>>(F, U, D, bn, rec, w.counters + 0);
         else if (c == 0)
