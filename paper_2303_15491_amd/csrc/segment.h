@@ -458,7 +458,15 @@ __global__ __launch_bounds__(NT, NT >= 512 && ZC <= 16 ? 6 : 1) void k_steepest(
     const bool xm = x > 0, xp = x < g.nx - 1;
     uint32_t my_min = 0, my_max = 0;
     for (int z = z0; z < z1; ++z) {
-        __syncthreads();  // the previous plane's readers are done: its buffers are free
+        // The plain scan's ring slot pn was read as pm by the previous plane:
+        // wait for its readers.  The square search needs no barrier here
+        // after its first plane: the staging plane was last read before the
+        // previous plane's last barrier, and the square slot it rewrites
+        // below (pn, the previous plane's pm) is written only after the
+        // next barrier, which every wave reaches after that plane's
+        // best-of-squares.  Its first plane waits for the prologue's square
+        // search to release the staging plane.
+        if (!kSquares || z == z0) __syncthreads();
         if (z + 1 < g.nz) store_plane(pn);  // plane z + 1, fetched one step ahead
         if (kSquares) {
             __syncthreads();
