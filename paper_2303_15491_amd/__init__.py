@@ -217,15 +217,32 @@ def segment(field, with_order: bool = False, workspace=None, stream=None, out=No
         if with_order:
             out["order"] = torch.empty(field.shape, dtype=torch.int32, device=dev)
         out["info"] = torch.empty(4, dtype=torch.int32, device=dev)
+    _check_outs(field, out, with_order)
     lib = library()
     ws = _workspace(lib.plmss_workspace_bytes(dims, code, int(with_order)), dev, workspace)
-    if with_order and out.get("order") is None:
-        raise ValueError("with_order needs an order tensor in out")
     job = Job(field.data_ptr(), dims, code, out["asc"].data_ptr(), out["desc"].data_ptr(),
               out["ms"].data_ptr(), out["order"].data_ptr() if with_order else None,
               out["info"].data_ptr())
     _check(lib.plmss_segment(ctypes.byref(job), _ptr(ws), ws.numel(), _stream(stream)), "plmss_segment")
     return out
+
+
+def _check_outs(field, out, with_order, what="output"):
+    """Outputs a kernel writes must hold exactly the field's vertices as
+    contiguous int32 device tensors (info: 4 entries); anything else would be
+    written past its end."""
+    torch = _torch()
+    for k in ("asc", "desc", "ms") + (("order",) if with_order else ()):
+        t = out.get(k)
+        if t is None and k == "order":
+            raise ValueError("with_order needs an order tensor in out")
+        if (t is None or not t.is_cuda or t.dtype != torch.int32 or not t.is_contiguous()
+                or t.numel() != field.numel()):
+            raise ValueError(f"{what} {k} must be a contiguous int32 device tensor of the field's size")
+    info = out.get("info")
+    if info is None or not info.is_cuda or info.dtype != torch.int32 or not info.is_contiguous() \
+            or info.numel() < 4:
+        raise ValueError(f"{what} info must be a contiguous int32 device tensor of 4 entries")
 
 
 def _segment_outs(field, with_order):
@@ -245,8 +262,7 @@ def segment_static(field, with_order: bool = False, stream=None, out=None):
     code = _field_check(field)
     if out is None:
         out = _segment_outs(field, with_order)
-    if with_order and out.get("order") is None:
-        raise ValueError("with_order needs an order tensor in out")
+    _check_outs(field, out, with_order)
     job = Job(field.data_ptr(), dims_of(field.shape), code, out["asc"].data_ptr(), out["desc"].data_ptr(),
               out["ms"].data_ptr(), out["order"].data_ptr() if with_order else None,
               out["info"].data_ptr())

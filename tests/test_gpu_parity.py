@@ -108,6 +108,51 @@ def test_launch_shapes_keep_results(torch, knobs):
         plmss.tune_set(**saved)
 
 
+@pytest.mark.parametrize("shape,offset", [((40, 24, 96), 0), ((40, 24, 97), 0), ((40, 24, 96), 1)])
+def test_whole_line_rows_and_the_rest(torch, shape, offset):
+    """A field whose label rows are whole 128-byte lines (x a multiple of 32,
+    arrays on line boundaries) takes the streaming chase and MS write-back;
+    one with a ragged x, or with label arrays one element off a line, takes
+    the plain ones.  Both give the oracle's labels."""
+    f = fields.smoothed_noise(shape, 1.5, seed=11)
+    ref = oracle.segment(f)
+    n = f.size
+    buf = {k: torch.empty(n + 64, dtype=torch.int32, device="cuda") for k in ("asc", "desc", "ms")}
+    out = {k: buf[k][offset:offset + n].view(shape) for k in buf}
+    out["info"] = torch.empty(4, dtype=torch.int32, device="cuda")
+    _say(f"whole lines shape={shape} offset={offset}")
+    plmss.segment(_dev(torch, f), out=out)
+    torch.cuda.synchronize()
+    for k in ("asc", "desc", "ms"):
+        np.testing.assert_array_equal(_host(out[k]), ref[k], err_msg=f"{shape} {offset} {k}")
+    assert _host(out["info"]).tolist()[:4] == [0, ref["n_min"], ref["n_max"], ref["K"]]
+
+
+def test_segment_rejects_outputs_of_the_wrong_form(torch):
+    """Output tensors are checked before any launch: a short, mistyped,
+    strided or host tensor would otherwise be written past its end."""
+    f = _dev(torch, fields.smoothed_noise((16, 20, 24), 1.5, seed=12))
+    good = {k: torch.empty(f.shape, dtype=torch.int32, device="cuda") for k in ("asc", "desc", "ms")}
+    good["info"] = torch.empty(4, dtype=torch.int32, device="cuda")
+    bad_outs = [
+        dict(good, asc=torch.empty(f.numel() - 1, dtype=torch.int32, device="cuda")),
+        dict(good, desc=torch.empty(f.shape, dtype=torch.int64, device="cuda")),
+        dict(good, ms=torch.empty(f.numel() * 2, dtype=torch.int32, device="cuda")[::2]),
+        dict(good, ms=torch.empty(f.shape, dtype=torch.int32)),
+        dict(good, info=torch.empty(3, dtype=torch.int32, device="cuda")),
+        {k: v for k, v in good.items() if k != "info"},
+    ]
+    for fn in (plmss.segment, plmss.segment_static):
+        for o in bad_outs:
+            with pytest.raises(ValueError):
+                fn(f, out=o)
+        with pytest.raises(ValueError):
+            fn(f, with_order=True, out=good)  # no order tensor
+        fn(f, out=good)
+    torch.cuda.synchronize()
+    assert _host(good["info"])[0] == 0
+
+
 def test_degenerate_dims(torch):
     _compare_full(torch, np.arange(1000, dtype=np.float32), True, "line")
     _compare_full(torch, np.array([1.5], np.float32), True, "single")
