@@ -169,7 +169,7 @@ def _same(a, b) -> bool:
     return all(_same(x, y) for x, y in zip(a, b))
 
 
-def tune_segment(field, with_order: bool = False, reps: int = 3, use_cache: bool = True, log=None) -> dict:
+def tune_segment(field, with_order: bool = False, reps: int = 5, use_cache: bool = True, log=None) -> dict:
     """Tunes the single-field path on ``field`` (a device tensor); returns
     {"key", "knobs", "ms", "baseline_ms", "cached"}."""
     import torch
@@ -205,7 +205,7 @@ def segment_workspace(field, with_order: bool) -> int:
     return workspace_bytes(field.shape, field.dtype, with_order)
 
 
-def tune_batch(fields, reps: int = 3, use_cache: bool = True, log=None) -> dict:
+def tune_batch(fields, reps: int = 5, use_cache: bool = True, log=None) -> dict:
     """Tunes capacity-plan launches (hipGraph replays) on a batch of device
     fields; a fresh plan is built per candidate, since a plan keeps the scan
     depth it was created with and its graph the grids it was captured with."""
