@@ -596,8 +596,9 @@ void launch_steepest_any(int c, int zc, const Fields& F, unsigned grid, int32_t 
 }
 
 // A launch over one field whose label rows are whole cache lines (the
-// kernels' STREAM forms, segment.h kWholeLines); 3-D fields only, the shape
-// that the 512^3 and batch workloads take.
+// kernels' STREAM forms, segment.h kWholeLines).  Only 3-D fields have the
+// streaming forms compiled; batches and plans keep the plain ones, since
+// their fields' rows rarely fill whole lines.
 bool whole_lines(const Fields& F) { return F.table == nullptr && (F.one.flags & kWholeLines); }
 
 template <bool CHASE>
