@@ -59,6 +59,23 @@ def test_batch_matches_oracle(torch):
         _check_one(f, o, f"field {i} {f.shape}")
 
 
+@pytest.mark.parametrize("pair_stream", [0, 1])
+def test_batch_pair_sort_cached_or_streamed(torch, pair_stream):
+    """The batch's pair sort streams its loads by default; the cached form
+    (and the forced streamed form) give the same labels."""
+    saved = plmss.tune_get()
+    try:
+        plmss.tune_set(pair_stream=pair_stream)
+        fs = _mixed_fields(seed=3)
+        _say(f"batch pair_stream={pair_stream}")
+        outs = plmss.segment_batch([torch.from_numpy(f).cuda() for f in fs])
+        torch.cuda.synchronize()
+        for i, (f, o) in enumerate(zip(fs, outs)):
+            _check_one(f, o, f"pair_stream {pair_stream} field {i} {f.shape}")
+    finally:
+        plmss.tune_set(**saved)
+
+
 def test_batch_isolation_position_and_neighbours(torch):
     fs = _mixed_fields(1)
     target = fields.smoothed_noise((24, 33, 65), 1.5, seed=7)
