@@ -6,8 +6,10 @@
 // its position minus vbase_j.  Ties of value fall to the id, as for one field,
 // because launch-wide ids follow field-local ids within a field.
 //
-// The passes: a gather writes (key, launch-wide id) items; the usual LSD
-// passes sort them by key, the last of them storing each item's field index
+// The passes: a gather writes each vertex's key at its launch-wide id; the
+// first LSD pass reads those keys with the ids generated from their
+// positions (IndexValSrc), and it and the usual LSD passes after it sort the
+// (key, id) items by key, the last of them storing each item's field index
 // (found from its id) in place of the key; then passes over the digits of
 // the field index make the field the most significant part; the last of
 // them feeds the inversion by id chunks, whose final kernel writes each
@@ -33,14 +35,13 @@ __device__ __forceinline__ uint32_t field_index_of_vertex(const Fields& F, uint3
     return lo;
 }
 
-// The items of a batch in launch-wide order: item g is (key of field j's value
-// at g - vbase_j, g).  32-bit keys are packed with the id in one word (key in
-// the high half); 64-bit keys go to keys[] and the ids to ids[].  A NaN sets
-// its field's info[0].  Grid: one block per kTile vertices of the length
+// The keys of a batch in launch-wide order: keys[g] = key of field j's value
+// at g - vbase_j (the id g is implied by the position).  A NaN sets its
+// field's info[0].  Grid: one block per kTile vertices of the length
 // count_ptr points to (or n); blocks past it exit.
-template <typename T>
+template <typename T, typename K>
 __global__ __launch_bounds__(kBlock) void k_batch_keys(Fields F, const uint32_t* count_ptr, uint32_t n_host,
-                                                       uint64_t* keys, uint32_t* ids) {
+                                                       K* keys) {
     const uint32_t n = load_count(count_ptr, n_host);
     const uint32_t lo = blockIdx.x * uint32_t(kTile);
     if (lo >= n) return;
@@ -66,13 +67,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_keys(Fields F, const uint32_t*
             int32_t* info = gmem(F.table)[f].info;
             if (info) gmem(info)[0] = -4;  // PLMSS_E_NAN
         }
-        const auto k = sos_key(v);
-        if constexpr (sizeof(T) == 4) {
-            keys[g] = (uint64_t(k) << 32) | g;
-        } else {
-            keys[g] = k;
-            ids[g] = g;
-        }
+        keys[g] = sos_key(v);
     }
 }
 

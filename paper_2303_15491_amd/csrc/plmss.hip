@@ -469,20 +469,32 @@ void order_batch_sort(const Fields& all, const uint32_t* cnt, uint32_t n, uint32
     const unsigned workers = order_workers(n);
     uint64_t* kv0 = reinterpret_cast<uint64_t*>(w.keys[0]);
     uint64_t* kv1 = reinterpret_cast<uint64_t*>(w.keys[1]);
-    launch(PLMSS_KERNEL_ORDER_FIRST, s, [&] { k_batch_keys<T><<<tiles, kBlock, 0, s>>>(all, cnt, n, kv0, w.vals[0]); });
     const PackedItems pk{{kv0, kv1}, w.vals[1], w.npad};
     int cur = 0;
+    int shift0 = 0;  // the key passes still to run on packed items start here
     if constexpr (sizeof(T) == 8) {
-        // 64-bit keys: the low four digits as a key array and an id array,
-        // the fourth pass packing each key's high half with its id
+        // 64-bit keys: the low four digits as a key array and an id array
+        // (the first pass generating the ids), the fourth pass packing each
+        // key's high half with its id
+        launch(PLMSS_KERNEL_ORDER_FIRST, s,
+               [&] { k_batch_keys<T, uint64_t><<<tiles, kBlock, 0, s>>>(all, cnt, n, kv0); });
         const SplitItems<uint64_t> sp{{kv0, kv1}, {w.vals[0], w.vals[1]}};
-        radix_pass(sp.src(0), sp.dst(1), cnt, n, workers, 0, false, w, nullptr, s, kOrderKinds);
+        radix_pass(IndexValSrc<uint64_t>{kv0}, sp.dst(1), cnt, n, workers, 0, false, w, nullptr, s, kOrderKinds);
         radix_pass(sp.src(1), sp.dst(0), cnt, n, workers, kRadixBits, false, w, nullptr, s, kOrderKinds);
         radix_pass(sp.src(0), sp.dst(1), cnt, n, workers, 2 * kRadixBits, false, w, nullptr, s, kOrderKinds);
         radix_pass(sp.src(1), HighPackedDst{kv0}, cnt, n, workers, 3 * kRadixBits, false, w, nullptr, s,
                    kOrderKinds);
+    } else {
+        // 32-bit keys in a 4-byte array; the first pass generates the ids
+        // and leaves (key, id) packed in one word
+        launch(PLMSS_KERNEL_ORDER_FIRST, s,
+               [&] { k_batch_keys<T, uint32_t><<<tiles, kBlock, 0, s>>>(all, cnt, n, w.vals[0]); });
+        radix_pass(IndexValSrc<uint32_t>{w.vals[0]}, pk.dst(1), cnt, n, workers, 0, false, w, nullptr, s,
+                   kOrderKinds);
+        cur = 1;
+        shift0 = kRadixBits;
     }
-    for (int shift = 0; shift < 32; shift += kRadixBits) {
+    for (int shift = shift0; shift < 32; shift += kRadixBits) {
         // the last key pass stores each item's field index in place of its key
         if (shift + kRadixBits < 32)
             radix_pass(pk.src(cur), pk.dst(cur ^ 1), cnt, n, workers, shift, false, w, nullptr, s, kOrderKinds);
